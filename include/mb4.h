@@ -1,0 +1,185 @@
+/*
+ * mb4.h - C ABI of the MI355X (gfx950) MB4 integrator for the periodic 2D
+ * lattice nonlinear Schroedinger-type equation.
+ *
+ * Method: Sakai, Kudo, Imachi, Miyatake, Hoshi, Yamamoto, "A Parallelizable
+ * Energy-Preserving Integrator MB4 and Its Application to Quantum-Mechanical
+ * Wavepacket Dynamics", arXiv 2003.04345 (Sec. 2.2, Sec. 2.3, Algorithm 1).
+ *
+ * Problem.  psi in C^{nx*ny}, site (x, y) at index y*nx + x (x fastest, as in
+ * Sec. 2.1).  The flow is
+ *     i dpsi/dt = (K + V) psi + g |psi|^2 psi,
+ * with K = -t_hop on the four periodic nearest-neighbour links plus
+ * diag_shift on the diagonal, and V the on-site potential.  In the paper's
+ * notation (Eq. dNLS) this is gamma = -g; its K = -Laplacian_h (Eq.
+ * Kdefinition) is t_hop = 1/h_x^2, diag_shift = 4/h_x^2.  With
+ * u = (p, q) = (Re psi, Im psi) the flow is u' = S grad H(u) (Eqs. EOM1,
+ * EOM2) with S = [[0, I], [-I, 0]] and
+ *     H = 1/2 (p^T A p + q^T A q) + g/4 sum_j |psi_j|^4,   A = K + V,
+ * which is half of the paper's H (Eqs. U_K - U_E) and gives the same flow.
+ *
+ * One call of mb4_step advances one MB4 step per requested step: the
+ * simplified Newton iteration on the stage system (Eqs. Phidefinition,
+ * Newton1) with the Jacobian frozen at u_0 (Eq. Jacobian2), decoupled by the
+ * eigendecomposition of E into three stage solves (Eqs. MB4_4 - MB4_6) that
+ * run concurrently in one kernel, until ||r||_inf <= eps * ||u_0||_inf, then
+ * u_1 = U_{c_3} (c_3 = 1).  All arithmetic is IEEE double on the GPU.
+ *
+ * Conventions for every entry point.
+ *  - Return value: MB4_OK (0) or a negative MB4_E* code; mb4_strerror gives a
+ *    static string, mb4_error_detail a message for the calling thread's last
+ *    failure.
+ *  - Arguments are validated on the host before any device call, so invalid
+ *    calls return MB4_EINVAL even on a machine without a GPU.
+ *  - "host" pointers are ordinary CPU memory, read (or written) during the
+ *    call only; the library copies what it keeps and never retains caller
+ *    pointers.  "device" pointers are GPU memory of the state's device.
+ *  - A state is used by one host thread at a time.  All its work runs on the
+ *    stream given at creation (NULL is the null stream); every entry point
+ *    returns after that work is complete.
+ */
+#ifndef MB4_H
+#define MB4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define MB4_API __attribute__((visibility("default")))
+#else
+#define MB4_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MB4_OK 0
+#define MB4_EINVAL (-1)   /* invalid argument: NULL, non-finite, size limits */
+#define MB4_ENOMEM (-2)   /* footprint above mem_budget or allocation failed */
+#define MB4_EDEVICE (-3)  /* a HIP runtime call failed */
+#define MB4_ENOCONV (-4)  /* simplified Newton did not converge (Sec. 2.2) */
+
+/* Periodic lattice.  nx, ny >= 3; nx * ny <= 2^28.  t_hop and diag_shift
+ * finite. */
+typedef struct {
+  int32_t nx, ny;
+  double t_hop;
+  double diag_shift;
+} mb4_lattice;
+
+/* Cubic on-site nonlinearity g |psi|^2 psi (g = -gamma of the paper). */
+typedef struct {
+  double g;
+} mb4_nonlinearity;
+
+/* Solver options; pass NULL for all defaults, or start from
+ * mb4_options_default().  Zero in a numeric field selects its default. */
+typedef struct {
+  double eps;            /* Newton tolerance relative to ||u_0||_inf; default 1e-13
+                            (the paper's epsilon, Sec. 3, read as relative) */
+  int32_t max_newton;    /* Newton iterations before MB4_ENOCONV; default 50, <= 1000 */
+  int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve; default 4, <= 64 */
+  void* stream;          /* hipStream_t for all work of the state; NULL = null stream */
+  uint64_t mem_budget;   /* bytes of device memory the state may allocate; 0 = no limit */
+} mb4_options;
+
+typedef struct mb4_state mb4_state;
+
+/* Fills *opt with the defaults.  NULL-safe. */
+MB4_API void mb4_options_default(mb4_options* opt);
+
+/* Creates a state on the current HIP device.
+ *  lattice, nonlinearity: host structs as above.
+ *  potential: host array of nx*ny finite doubles V_j (copied).
+ *  h: time step, finite and non-zero (negative steps run backwards).
+ *  opt: NULL or options.
+ *  out: receives the new state; set to NULL on failure.
+ * The initial state psi is zero until mb4_set_state*.  Device memory: 264
+ * bytes per site (potential, u_0, two stage-value fields, the transformed
+ * residual and two stage-correction fields) plus a few kilobytes.
+ * Errors: MB4_EINVAL, MB4_ENOMEM, MB4_EDEVICE. */
+MB4_API int mb4_create(const mb4_lattice* lattice, const double* potential,
+               const mb4_nonlinearity* nonlinearity, double h,
+               const mb4_options* opt, mb4_state** out);
+
+/* Frees all device memory of the state.  NULL-safe. */
+MB4_API void mb4_destroy(mb4_state* state);
+
+/* Sets psi = p + i q from host arrays of nx*ny finite doubles (copied) and
+ * resets the step counter.  Errors: MB4_EINVAL, MB4_EDEVICE. */
+MB4_API int mb4_set_state(mb4_state* state, const double* p, const double* q);
+
+/* Copies psi to host arrays p, q of nx*ny doubles. */
+MB4_API int mb4_get_state(mb4_state* state, double* p, double* q);
+
+/* As mb4_set_state / mb4_get_state with device arrays of nx*ny doubles. The
+ * caller orders its own work on these arrays with the state's stream.  No
+ * finiteness check is made on device input. */
+MB4_API int mb4_set_state_device(mb4_state* state, const double* d_p, const double* d_q);
+MB4_API int mb4_get_state_device(mb4_state* state, double* d_p, double* d_q);
+
+/* Advances nsteps >= 0 MB4 steps (Algorithm 1, time loop).  Each step is
+ * all-or-nothing: if the Newton loop of a step does not reach the tolerance
+ * within max_newton iterations (or produces a non-finite update), the call
+ * returns MB4_ENOCONV and the state keeps the last accepted step;
+ * mb4_steps_done tells how far the run got, and the caller may lower h with
+ * mb4_set_h and continue (Sec. 2.2 advises this remedy). */
+MB4_API int mb4_step(mb4_state* state, int64_t nsteps);
+
+/* H of the current state, in the convention above (Sec. 2.1, Eqs. U_K - U_E,
+ * halved).  Summed on the GPU in a fixed order with compensated (TwoSum)
+ * arithmetic. */
+MB4_API int mb4_energy(mb4_state* state, double* H);
+
+/* out[0..5] = H, U_K, U_I, U_E, sum |psi|^2, sum |psi|^4 with
+ * U_K = psi^H K psi / 2, U_I = g/4 sum |psi|^4, U_E = psi^H V psi / 2;
+ * sum |psi|^4 is the participation ratio of Sec. 3.2. */
+MB4_API int mb4_energy_components(mb4_state* state, double out[6]);
+
+/* Changes the time step (finite, non-zero). */
+MB4_API int mb4_set_h(mb4_state* state, double h);
+
+/* Steps accepted since the last mb4_set_state*; -1 for NULL. */
+MB4_API int64_t mb4_steps_done(const mb4_state* state);
+
+/* Statistics of the last accepted step: Newton iterations, block-Jacobi
+ * sweeps per stage solve summed over the iterations, and ||r||_inf of the
+ * last Newton update.  Any output pointer may be NULL. */
+MB4_API int mb4_last_stats(const mb4_state* state, int32_t* newton_iters,
+                   int32_t* inner_sweeps, double* last_rnorm);
+
+/* Kernel-level entry points, for callers that drive the Newton loop
+ * themselves and for testing each kernel against a reference.  Stage fields
+ * are three stage-major planes of nx*ny sites, each site an interleaved
+ * (p, q) pair: element (i, site, comp) at d[(i*nx*ny + site)*2 + comp].
+ *
+ * mb4_newton_update: U <- U + (T (x) I) rbar if d_rbar != NULL (Eq. MB4_6
+ * and the update of Eq. Newton1), then d_phibar <- (T^-1 (x) I) Phi(U)
+ * (Eqs. Phidefinition, MB4_4) at the state's current psi as u_0, with the
+ * linear stage integrals by E (Eq. fKu2) and the cubic ones by 6-node
+ * Gauss-Legendre (exact for Eq. fIu2).  If rnorm != NULL it receives
+ * ||(T (x) I) rbar||_inf (0 when d_rbar is NULL).  d_U is read and written,
+ * d_rbar read, d_phibar written; all device. */
+MB4_API int mb4_newton_update(mb4_state* state, double* d_U, const double* d_rbar,
+                      double* d_phibar, double* rnorm);
+
+/* mb4_stage_solve: approximate solutions of the three decoupled stage
+ * systems (I - h lambda_i J) rbar_i = -phibar_i (Eq. MB4_5) with J frozen at
+ * the state's psi (Eqs. JL, JR): exact 2x2 on-site block inverses and
+ * `sweeps` >= 1 block-Jacobi sweeps over the hopping links, starting from
+ * rbar = 0.  d_phibar read, d_rbar written; both device. */
+MB4_API int mb4_stage_solve(mb4_state* state, const double* d_phibar, double* d_rbar,
+                    int32_t sweeps);
+
+/* Static description of a status code. */
+MB4_API const char* mb4_strerror(int code);
+
+/* Message describing the calling thread's last failed call ("" if none). */
+MB4_API const char* mb4_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MB4_H */

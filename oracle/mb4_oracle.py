@@ -141,6 +141,10 @@ def method_constants(alpha1=ALPHA1_PAPER, c=C_PAPER) -> MB4Constants:
     order = np.argsort(np.real(lam))
     lam = np.real(lam)[order]
     t = np.real(t)[:, order]
+    # The scaling of each eigenvector is free (the Newton root does not depend
+    # on it); fix the sign so that the first row is positive, as the GPU side
+    # does, which makes the transformed quantities of both sides comparable.
+    t = t * np.where(t[0, :] < 0, -1.0, 1.0)[None, :]
     tinv = np.linalg.inv(t)
     # Eq. fIu2: |U_z|^2 U_z = sum_{a,b,d} conj(Y_a) Y_b Y_d l_a l_b l_d with
     # Y_0 = u_0, Y_j = U_{c_j}; the coefficient of each product in stage i

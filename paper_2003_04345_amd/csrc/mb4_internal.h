@@ -1,0 +1,82 @@
+// Internal interface between the MB4 runtime (mb4_runtime.hip) and its HIP
+// kernels (mb4_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mb4 {
+
+// Largest Newton iteration count a state may request; the stats block keeps
+// one ||r||_inf slot per iteration.
+constexpr int kMaxNewton = 1000;
+
+// Device-side step statistics.  Non-negative doubles are stored as their
+// IEEE bit patterns so that an unsigned 64-bit atomicMax is an exact,
+// order-independent maximum.
+struct Stats {
+  unsigned long long u0max;                 // ||u_0||_inf of the current step
+  unsigned long long rmax[kMaxNewton + 1];  // rmax[l] = ||r^l||_inf, l >= 1
+};
+
+// The lattice problem as the kernels see it: periodic nx x ny, hopping -t on
+// the four links, on-site A_jj = V_j + shift, nonlinearity g, time step h.
+struct Lattice {
+  int nx, ny;
+  double t, shift, g, h;
+  const double* V;     // [nx*ny]
+  const double2* u0;   // [nx*ny] (p, q)
+};
+
+struct Planes3 {
+  double2* s[3];
+};
+
+struct CPlanes3 {
+  const double2* s[3];
+};
+
+// Early-exit test shared by all kernels of Newton iteration l >= 2: the
+// iteration is skipped once ||r^{l-1}||_inf <= eps * max(||u_0||_inf, tiny).
+struct ConvCheck {
+  const Stats* stats;  // NULL: never skip
+  int prev;            // index of the iteration whose norm decides
+  double eps;
+};
+
+// Kernel launchers (each enqueues on `stream`; return hipSuccess or an error).
+hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream);
+
+// Transformed residual at U = e_3 (x) u_0: phib_i = -h TC_i f(u_0); records
+// ||u_0||_inf.
+hipError_t launch_first_residual(const Lattice& lat, Planes3 phib, Stats* stats,
+                                 hipStream_t stream);
+
+// Uout <- base + (T (x) I) rbar (base = Uin, or e_3 (x) u_0 if from_u0), then
+// phib <- (T^-1 (x) I) Phi(Uout); ||(T (x) I) rbar||_inf goes to *rslot (if
+// not NULL).  Uin and Uout must not alias: blocks read the halo of Uin while
+// others write Uout.  Uout is not written when !from_u0 && !has_rbar.
+hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
+                                  bool has_rbar, bool from_u0, Planes3 phib,
+                                  unsigned long long* rslot, ConvCheck check,
+                                  hipStream_t stream);
+
+// One block-Jacobi sweep for the three stage systems (I - h lambda_i J) r_i
+// = -phib_i; first == true starts from r = 0 (rin ignored).  rin and rout
+// must not alias.
+hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
+                              bool first, ConvCheck check, hipStream_t stream);
+
+// (p, q) arrays <-> interleaved double2 field of n sites.
+hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,
+                             hipStream_t stream);
+hipError_t launch_deinterleave(const double2* in, double* p, double* q, int n,
+                               hipStream_t stream);
+
+// Energy components: H, U_K, U_I, U_E, sum n, sum n^2 into out[6] (device),
+// through `partials` (device scratch of energy_partials_count(nx, ny) doubles).
+size_t energy_partials_count(int nx, int ny);
+hipError_t launch_energy(const Lattice& lat, double* partials, double* out,
+                         hipStream_t stream);
+
+}  // namespace mb4

@@ -1,0 +1,540 @@
+// Host runtime and C ABI of the MB4 integrator (see include/mb4.h).
+//
+// A state owns the device fields of one lattice problem and drives
+// Algorithm 1 of Sakai et al. (arXiv 2003.04345) on one stream:
+//   per step: first transformed residual from u_0 (U^0 = e_3 (x) u_0), then
+//   Newton iterations l = 1, 2, ..., each = stage solve (k block-Jacobi
+//   sweeps, the three stages in one launch) + fused update/residual pass
+//   recording ||r^l||_inf.  Iterations are enqueued in batches sized by the
+//   previous step's count; every kernel of iteration l >= 2 returns at once
+//   when ||r^{l-1}||_inf already met the tolerance, so an over-long batch
+//   costs only empty launches.  One 8-byte-per-iteration read-back per batch
+//   decides acceptance on the host: u_1 = U_{c_3} becomes u_0 by a pointer
+//   swap (Sec. 2.2, last paragraph: c_3 = 1).
+#include <float.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "mb4.h"
+#include "mb4_internal.h"
+
+using mb4::CPlanes3;
+using mb4::ConvCheck;
+using mb4::Lattice;
+using mb4::Planes3;
+using mb4::Stats;
+
+namespace {
+
+constexpr double kDefaultEps = 1e-13;  // Sec. 3: epsilon = 1e-13
+constexpr int kDefaultMaxNewton = 50;
+constexpr int kDefaultSweeps = 4;
+constexpr int kMaxSweeps = 64;
+constexpr int64_t kMaxSites = int64_t(1) << 28;
+constexpr int kInitialPrediction = 3;
+
+thread_local std::string g_detail;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_detail = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(MB4_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+bool all_finite(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(v[i])) return false;
+  return true;
+}
+
+double conv_tol(double eps, double u0max) { return eps * (u0max > DBL_MIN ? u0max : DBL_MIN); }
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+}  // namespace
+
+struct mb4_state {
+  int nx = 0, ny = 0;
+  size_t sites = 0;
+  double t = 0, shift = 0, g = 0, h = 0;
+  double eps = kDefaultEps;
+  int max_newton = kDefaultMaxNewton;
+  int sweeps = kDefaultSweeps;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<void*> device_allocs;
+  std::vector<void*> host_allocs;
+  double* V = nullptr;
+  double2* u0 = nullptr;
+  double2* Ua[3] = {nullptr, nullptr, nullptr};
+  double2* Ub[3] = {nullptr, nullptr, nullptr};
+  double2* phib[3] = {nullptr, nullptr, nullptr};
+  double2* ra[3] = {nullptr, nullptr, nullptr};
+  double2* rb[3] = {nullptr, nullptr, nullptr};
+  Stats* stats = nullptr;
+  unsigned long long* h_stats = nullptr;  // pinned: u0max, rmax[0..kMaxNewton]
+  double* partials = nullptr;
+  double* eout = nullptr;
+  double* h_eout = nullptr;  // pinned, 6 doubles
+  int64_t steps_done = 0;
+  int last_iters = 0;
+  int last_sweeps = 0;
+  double last_rnorm = 0.0;
+  int predicted = kInitialPrediction;
+};
+
+namespace {
+
+// Device bytes of a state: V (8 B/site), u_0 (16), two stage-value fields
+// (2 x 48), the transformed residual (48), two stage-correction fields (2 x 48).
+size_t footprint_bytes(size_t sites, int nx, int ny) {
+  return sites * 264 + sizeof(Stats) + mb4::energy_partials_count(nx, ny) * sizeof(double) +
+         8 * sizeof(double);
+}
+
+int dalloc(mb4_state* s, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? MB4_ENOMEM : MB4_EDEVICE, "hipMalloc(%zu): %s", bytes,
+                hipGetErrorString(e));
+  }
+  s->device_allocs.push_back(*p);
+  return MB4_OK;
+}
+
+int halloc(mb4_state* s, void** p, size_t bytes) {
+  hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(MB4_EDEVICE, "hipHostMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  s->host_allocs.push_back(*p);
+  return MB4_OK;
+}
+
+void free_all(mb4_state* s) {
+  for (void* p : s->device_allocs) (void)hipFree(p);
+  for (void* p : s->host_allocs) (void)hipHostFree(p);
+  s->device_allocs.clear();
+  s->host_allocs.clear();
+}
+
+Lattice lattice_of(const mb4_state* s) {
+  Lattice L;
+  L.nx = s->nx;
+  L.ny = s->ny;
+  L.t = s->t;
+  L.shift = s->shift;
+  L.g = s->g;
+  L.h = s->h;
+  L.V = s->V;
+  L.u0 = s->u0;
+  return L;
+}
+
+Planes3 P(double2* const (&a)[3]) { return Planes3{{a[0], a[1], a[2]}}; }
+CPlanes3 C(double2* const (&a)[3]) { return CPlanes3{{a[0], a[1], a[2]}}; }
+
+Planes3 planes_of(double* base, size_t sites) {
+  double2* b = reinterpret_cast<double2*>(base);
+  return Planes3{{b, b + sites, b + 2 * sites}};
+}
+
+CPlanes3 cplanes_of(const double* base, size_t sites) {
+  const double2* b = reinterpret_cast<const double2*>(base);
+  return CPlanes3{{b, b + sites, b + 2 * sites}};
+}
+
+int use_device(const mb4_state* s) {
+  HIP_TRY(hipSetDevice(s->device));
+  return MB4_OK;
+}
+
+// Enqueues the stage solve of one Newton iteration: `sweeps` block-Jacobi
+// sweeps from r = 0 alternating between ra and rb; returns the planes that
+// hold the result.
+int enqueue_solve(mb4_state* s, const Lattice& L, CPlanes3 phib, ConvCheck chk,
+                  double2* const** result) {
+  for (int k = 0; k < s->sweeps; ++k) {
+    double2* const(&out)[3] = (k % 2 == 0) ? s->ra : s->rb;
+    double2* const(&in)[3] = (k % 2 == 0) ? s->rb : s->ra;
+    HIP_TRY(mb4::launch_stage_sweep(L, phib, C(in), P(out), k == 0, chk, s->stream));
+  }
+  *result = ((s->sweeps - 1) % 2 == 0) ? s->ra : s->rb;
+  return MB4_OK;
+}
+
+// One MB4 step (Algorithm 1, body of the time loop).
+int step_once(mb4_state* s) {
+  const Lattice L = lattice_of(s);
+  HIP_TRY(mb4::launch_reset_stats(s->stats, s->max_newton, s->stream));
+  HIP_TRY(mb4::launch_first_residual(L, P(s->phib), s->stats, s->stream));
+  int done = 0;
+  int batch = std::max(1, std::min(s->predicted, s->max_newton));
+  for (;;) {
+    const int upto = std::min(done + batch, s->max_newton);
+    for (int l = done + 1; l <= upto; ++l) {
+      const ConvCheck chk = (l >= 2) ? ConvCheck{s->stats, l - 1, s->eps}
+                                     : ConvCheck{nullptr, 0, 0.0};
+      double2* const* rfin = nullptr;
+      int rc = enqueue_solve(s, L, C(s->phib), chk, &rfin);
+      if (rc != MB4_OK) return rc;
+      // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
+      double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
+      double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
+      const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
+      HIP_TRY(mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
+                                          &s->stats->rmax[l], chk, s->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(s->h_stats, s->stats, sizeof(unsigned long long) * (upto + 2),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double u0max = bits_to_double(s->h_stats[0]);
+    const double tol = conv_tol(s->eps, u0max);
+    for (int l = done + 1; l <= upto; ++l) {
+      const double r = bits_to_double(s->h_stats[1 + l]);
+      if (r <= tol) {
+        double2** uout = (l % 2 == 1) ? s->Ua : s->Ub;
+        std::swap(s->u0, uout[2]);  // u_1 = U_{c_3}
+        s->last_iters = l;
+        s->last_sweeps = l * s->sweeps;
+        s->last_rnorm = r;
+        s->predicted = l;
+        return MB4_OK;
+      }
+      if (!isfinite(r))
+        return fail(MB4_ENOCONV, "non-finite Newton update at iteration %d", l);
+    }
+    if (upto >= s->max_newton)
+      return fail(MB4_ENOCONV, "no convergence in %d Newton iterations (||r||_inf = %.3e, tol %.3e)",
+                  s->max_newton, bits_to_double(s->h_stats[1 + upto]), tol);
+    done = upto;
+    batch = 1;
+  }
+}
+
+int check_state(const mb4_state* s) {
+  if (s == nullptr) return fail(MB4_EINVAL, "state is NULL");
+  return MB4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mb4_options_default(mb4_options* opt) {
+  if (opt == nullptr) return;
+  memset(opt, 0, sizeof(*opt));
+  opt->eps = kDefaultEps;
+  opt->max_newton = kDefaultMaxNewton;
+  opt->inner_sweeps = kDefaultSweeps;
+  opt->stream = nullptr;
+  opt->mem_budget = 0;
+}
+
+int mb4_create(const mb4_lattice* lattice, const double* potential,
+               const mb4_nonlinearity* nonlinearity, double h, const mb4_options* opt,
+               mb4_state** out) {
+  if (out == nullptr) return fail(MB4_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (lattice == nullptr || potential == nullptr || nonlinearity == nullptr)
+    return fail(MB4_EINVAL, "lattice, potential and nonlinearity must not be NULL");
+  if (lattice->nx < 3 || lattice->ny < 3)
+    return fail(MB4_EINVAL, "lattice sides must be >= 3 (got %d x %d)", lattice->nx, lattice->ny);
+  const int64_t sites = int64_t(lattice->nx) * int64_t(lattice->ny);
+  if (sites > kMaxSites) return fail(MB4_EINVAL, "lattice has more than 2^28 sites");
+  if (!isfinite(lattice->t_hop) || !isfinite(lattice->diag_shift))
+    return fail(MB4_EINVAL, "t_hop and diag_shift must be finite");
+  if (!isfinite(nonlinearity->g)) return fail(MB4_EINVAL, "g must be finite");
+  if (!isfinite(h) || h == 0.0) return fail(MB4_EINVAL, "h must be finite and non-zero");
+  mb4_options o;
+  mb4_options_default(&o);
+  if (opt != nullptr) {
+    if (!isfinite(opt->eps) || opt->eps < 0.0 || opt->eps >= 1.0)
+      return fail(MB4_EINVAL, "eps must be in [0, 1)");
+    if (opt->max_newton < 0 || opt->max_newton > mb4::kMaxNewton)
+      return fail(MB4_EINVAL, "max_newton must be in [0, %d]", mb4::kMaxNewton);
+    if (opt->inner_sweeps < 0 || opt->inner_sweeps > kMaxSweeps)
+      return fail(MB4_EINVAL, "inner_sweeps must be in [0, %d]", kMaxSweeps);
+    if (opt->eps > 0.0) o.eps = opt->eps;
+    if (opt->max_newton > 0) o.max_newton = opt->max_newton;
+    if (opt->inner_sweeps > 0) o.inner_sweeps = opt->inner_sweeps;
+    o.stream = opt->stream;
+    o.mem_budget = opt->mem_budget;
+  }
+  if (!all_finite(potential, size_t(sites)))
+    return fail(MB4_EINVAL, "potential has non-finite entries");
+  const size_t need = footprint_bytes(size_t(sites), lattice->nx, lattice->ny);
+  if (o.mem_budget != 0 && need > o.mem_budget)
+    return fail(MB4_ENOMEM, "state needs %zu bytes, above mem_budget %llu", need,
+                static_cast<unsigned long long>(o.mem_budget));
+
+  mb4_state* s = new (std::nothrow) mb4_state();
+  if (s == nullptr) return fail(MB4_ENOMEM, "host allocation failed");
+  s->nx = lattice->nx;
+  s->ny = lattice->ny;
+  s->sites = size_t(sites);
+  s->t = lattice->t_hop;
+  s->shift = lattice->diag_shift;
+  s->g = nonlinearity->g;
+  s->h = h;
+  s->eps = o.eps;
+  s->max_newton = o.max_newton;
+  s->sweeps = o.inner_sweeps;
+  s->stream = static_cast<hipStream_t>(o.stream);
+
+  int rc = MB4_OK;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) rc = fail(MB4_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  const size_t field = s->sites * sizeof(double2);
+  auto alloc_field = [&](double2** p) {
+    if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(p), field);
+  };
+  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->V), s->sites * sizeof(double));
+  alloc_field(&s->u0);
+  for (int i = 0; i < 3; ++i) {
+    alloc_field(&s->Ua[i]);
+    alloc_field(&s->Ub[i]);
+    alloc_field(&s->phib[i]);
+    alloc_field(&s->ra[i]);
+    alloc_field(&s->rb[i]);
+  }
+  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->stats), sizeof(Stats));
+  if (rc == MB4_OK)
+    rc = dalloc(s, reinterpret_cast<void**>(&s->partials),
+                mb4::energy_partials_count(s->nx, s->ny) * sizeof(double));
+  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->eout), 8 * sizeof(double));
+  if (rc == MB4_OK)
+    rc = halloc(s, reinterpret_cast<void**>(&s->h_stats), sizeof(Stats));
+  if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_eout), 8 * sizeof(double));
+  if (rc == MB4_OK) {
+    e = hipMemcpyAsync(s->V, potential, s->sites * sizeof(double), hipMemcpyHostToDevice,
+                       s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->u0, 0, field, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->stats, 0, sizeof(Stats), s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) rc = fail(MB4_EDEVICE, "initial upload: %s", hipGetErrorString(e));
+  }
+  if (rc != MB4_OK) {
+    free_all(s);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return MB4_OK;
+}
+
+void mb4_destroy(mb4_state* state) {
+  if (state == nullptr) return;
+  (void)hipSetDevice(state->device);
+  (void)hipStreamSynchronize(state->stream);
+  free_all(state);
+  delete state;
+}
+
+int mb4_set_state(mb4_state* s, const double* p, const double* q) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (p == nullptr || q == nullptr) return fail(MB4_EINVAL, "p and q must not be NULL");
+  if (!all_finite(p, s->sites) || !all_finite(q, s->sites))
+    return fail(MB4_EINVAL, "state has non-finite entries");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  std::vector<double> buf(2 * s->sites);
+  for (size_t i = 0; i < s->sites; ++i) {
+    buf[2 * i] = p[i];
+    buf[2 * i + 1] = q[i];
+  }
+  HIP_TRY(hipMemcpyAsync(s->u0, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->steps_done = 0;
+  s->predicted = kInitialPrediction;
+  return MB4_OK;
+}
+
+int mb4_get_state(mb4_state* s, double* p, double* q) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (p == nullptr || q == nullptr) return fail(MB4_EINVAL, "p and q must not be NULL");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  std::vector<double> buf(2 * s->sites);
+  HIP_TRY(hipMemcpyAsync(buf.data(), s->u0, buf.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (size_t i = 0; i < s->sites; ++i) {
+    p[i] = buf[2 * i];
+    q[i] = buf[2 * i + 1];
+  }
+  return MB4_OK;
+}
+
+int mb4_set_state_device(mb4_state* s, const double* d_p, const double* d_q) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (d_p == nullptr || d_q == nullptr) return fail(MB4_EINVAL, "d_p and d_q must not be NULL");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  HIP_TRY(mb4::launch_interleave(d_p, d_q, s->u0, int(s->sites), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->steps_done = 0;
+  s->predicted = kInitialPrediction;
+  return MB4_OK;
+}
+
+int mb4_get_state_device(mb4_state* s, double* d_p, double* d_q) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (d_p == nullptr || d_q == nullptr) return fail(MB4_EINVAL, "d_p and d_q must not be NULL");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  HIP_TRY(mb4::launch_deinterleave(s->u0, d_p, d_q, int(s->sites), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MB4_OK;
+}
+
+int mb4_step(mb4_state* s, int64_t nsteps) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (nsteps < 0) return fail(MB4_EINVAL, "nsteps must be >= 0");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    rc = step_once(s);
+    if (rc != MB4_OK) return rc;
+    ++s->steps_done;
+  }
+  return MB4_OK;
+}
+
+int mb4_energy_components(mb4_state* s, double out[6]) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (out == nullptr) return fail(MB4_EINVAL, "out must not be NULL");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  HIP_TRY(mb4::launch_energy(lattice_of(s), s->partials, s->eout, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->h_eout, s->eout, 6 * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < 6; ++k) out[k] = s->h_eout[k];
+  return MB4_OK;
+}
+
+int mb4_energy(mb4_state* s, double* H) {
+  if (H == nullptr) return fail(MB4_EINVAL, "H must not be NULL");
+  double comp[6];
+  const int rc = mb4_energy_components(s, comp);
+  if (rc == MB4_OK) *H = comp[0];
+  return rc;
+}
+
+int mb4_set_h(mb4_state* s, double h) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (!isfinite(h) || h == 0.0) return fail(MB4_EINVAL, "h must be finite and non-zero");
+  s->h = h;
+  return MB4_OK;
+}
+
+int64_t mb4_steps_done(const mb4_state* s) { return s == nullptr ? -1 : s->steps_done; }
+
+int mb4_last_stats(const mb4_state* s, int32_t* newton_iters, int32_t* inner_sweeps,
+                   double* last_rnorm) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (newton_iters) *newton_iters = s->last_iters;
+  if (inner_sweeps) *inner_sweeps = s->last_sweeps;
+  if (last_rnorm) *last_rnorm = s->last_rnorm;
+  return MB4_OK;
+}
+
+int mb4_newton_update(mb4_state* s, double* d_U, const double* d_rbar, double* d_phibar,
+                      double* rnorm) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (d_U == nullptr || d_phibar == nullptr)
+    return fail(MB4_EINVAL, "d_U and d_phibar must not be NULL");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  const bool has_r = d_rbar != nullptr;
+  const CPlanes3 uin = cplanes_of(d_U, s->sites);
+  const CPlanes3 rin = has_r ? cplanes_of(d_rbar, s->sites) : CPlanes3{{nullptr, nullptr, nullptr}};
+  HIP_TRY(mb4::launch_reset_stats(s->stats, 0, s->stream));
+  HIP_TRY(mb4::launch_update_residual(lattice_of(s), uin, P(s->Ua), rin, has_r, false,
+                                      planes_of(d_phibar, s->sites), &s->stats->rmax[0],
+                                      ConvCheck{nullptr, 0, 0.0}, s->stream));
+  if (has_r) {
+    // The pass cannot update U in place (other blocks read its halo), so the
+    // result goes through the state's stage buffer.
+    const Planes3 uout = planes_of(d_U, s->sites);
+    for (int i = 0; i < 3; ++i)
+      HIP_TRY(hipMemcpyAsync(uout.s[i], s->Ua[i], s->sites * sizeof(double2),
+                             hipMemcpyDeviceToDevice, s->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(s->h_stats, s->stats, 2 * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (rnorm) *rnorm = bits_to_double(s->h_stats[1]);
+  return MB4_OK;
+}
+
+int mb4_stage_solve(mb4_state* s, const double* d_phibar, double* d_rbar, int32_t sweeps) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (d_phibar == nullptr || d_rbar == nullptr)
+    return fail(MB4_EINVAL, "d_phibar and d_rbar must not be NULL");
+  if (sweeps < 1 || sweeps > kMaxSweeps)
+    return fail(MB4_EINVAL, "sweeps must be in [1, %d]", kMaxSweeps);
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  const Lattice L = lattice_of(s);
+  const CPlanes3 ph = cplanes_of(d_phibar, s->sites);
+  const Planes3 ext = planes_of(d_rbar, s->sites);
+  Planes3 prev{{nullptr, nullptr, nullptr}};
+  for (int k = 0; k < sweeps; ++k) {
+    const Planes3 out = (k == sweeps - 1) ? ext : ((k % 2 == 0) ? P(s->ra) : P(s->rb));
+    const CPlanes3 in{{prev.s[0], prev.s[1], prev.s[2]}};
+    HIP_TRY(mb4::launch_stage_sweep(L, ph, in, out, k == 0, ConvCheck{nullptr, 0, 0.0},
+                                    s->stream));
+    prev = out;
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MB4_OK;
+}
+
+const char* mb4_strerror(int code) {
+  switch (code) {
+    case MB4_OK:
+      return "success";
+    case MB4_EINVAL:
+      return "invalid argument";
+    case MB4_ENOMEM:
+      return "out of memory or above the memory budget";
+    case MB4_EDEVICE:
+      return "HIP runtime error";
+    case MB4_ENOCONV:
+      return "simplified Newton iteration did not converge";
+    default:
+      return "unknown status code";
+  }
+}
+
+const char* mb4_error_detail(void) { return g_detail.c_str(); }
+
+}  // extern "C"

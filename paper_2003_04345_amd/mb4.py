@@ -1,0 +1,279 @@
+"""ctypes binding of libmb4.so, the MI355X MB4 integrator (include/mb4.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Functions keep the C names; host arrays are numpy float64
+arrays, device arrays are raw device pointers (ints), e.g. a torch tensor's
+``data_ptr()``.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_int, c_int32,
+                    c_int64, c_uint64, c_void_p)
+
+import numpy as np
+
+MB4_OK = 0
+MB4_EINVAL = -1
+MB4_ENOMEM = -2
+MB4_EDEVICE = -3
+MB4_ENOCONV = -4
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmb4.so")
+
+
+class mb4_lattice(Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("t_hop", c_double), ("diag_shift", c_double)]
+
+
+class mb4_nonlinearity(Structure):
+    _fields_ = [("g", c_double)]
+
+
+class mb4_options(Structure):
+    _fields_ = [("eps", c_double), ("max_newton", c_int32), ("inner_sweeps", c_int32),
+                ("stream", c_void_p), ("mem_budget", c_uint64)]
+
+
+class Mb4Error(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        self.code = code
+        super().__init__(f"{where}: {detail or strerror(code)} (code {code})")
+
+
+_lib = None
+
+_SIGNATURES = {
+    "mb4_options_default": (None, [POINTER(mb4_options)]),
+    "mb4_create": (c_int, [POINTER(mb4_lattice), POINTER(c_double), POINTER(mb4_nonlinearity),
+                           c_double, POINTER(mb4_options), POINTER(c_void_p)]),
+    "mb4_destroy": (None, [c_void_p]),
+    "mb4_set_state": (c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "mb4_get_state": (c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "mb4_set_state_device": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "mb4_get_state_device": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "mb4_step": (c_int, [c_void_p, c_int64]),
+    "mb4_energy": (c_int, [c_void_p, POINTER(c_double)]),
+    "mb4_energy_components": (c_int, [c_void_p, POINTER(c_double)]),
+    "mb4_set_h": (c_int, [c_void_p, c_double]),
+    "mb4_steps_done": (c_int64, [c_void_p]),
+    "mb4_last_stats": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]),
+    "mb4_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    "mb4_stage_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_int32]),
+    "mb4_strerror": (c_char_p, [c_int]),
+    "mb4_error_detail": (c_char_p, []),
+}
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Loads libmb4.so (once).  Raises FileNotFoundError if it is not built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(
+            f"{p} is missing: build it with `python -m paper_2003_04345_amd._build`")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().mb4_strerror(code).decode()
+
+
+def error_detail() -> str:
+    return load_library().mb4_error_detail().decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != MB4_OK:
+        raise Mb4Error(rc, where, error_detail())
+    return rc
+
+
+def _host(a, n: int) -> np.ndarray:
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if arr.size != n:
+        raise ValueError(f"expected {n} values, got {arr.size}")
+    return arr
+
+
+def _dptr(a) -> int:
+    return a if isinstance(a, int) else int(a.data_ptr())
+
+
+def mb4_options_default() -> mb4_options:
+    o = mb4_options()
+    load_library().mb4_options_default(byref(o))
+    return o
+
+
+def mb4_create(lattice: mb4_lattice, potential, nonlinearity: mb4_nonlinearity, h: float,
+               opt: mb4_options | None = None) -> c_void_p:
+    """Creates a state; raises Mb4Error on failure (see mb4_create in mb4.h)."""
+    n = int(lattice.nx) * int(lattice.ny)
+    v = _host(potential, n) if n > 0 else np.zeros(1)
+    out = c_void_p()
+    rc = load_library().mb4_create(byref(lattice), v.ctypes.data_as(POINTER(c_double)),
+                                   byref(nonlinearity), float(h),
+                                   byref(opt) if opt is not None else None, byref(out))
+    _check(rc, "mb4_create")
+    return out
+
+
+def mb4_destroy(state) -> None:
+    load_library().mb4_destroy(state)
+
+
+def mb4_set_state(state, p, q, sites: int) -> None:
+    p = _host(p, sites)
+    q = _host(q, sites)
+    _check(load_library().mb4_set_state(state, p.ctypes.data_as(POINTER(c_double)),
+                                        q.ctypes.data_as(POINTER(c_double))), "mb4_set_state")
+
+
+def mb4_get_state(state, sites: int) -> tuple[np.ndarray, np.ndarray]:
+    p = np.empty(sites)
+    q = np.empty(sites)
+    _check(load_library().mb4_get_state(state, p.ctypes.data_as(POINTER(c_double)),
+                                        q.ctypes.data_as(POINTER(c_double))), "mb4_get_state")
+    return p, q
+
+
+def mb4_set_state_device(state, d_p, d_q) -> None:
+    _check(load_library().mb4_set_state_device(state, _dptr(d_p), _dptr(d_q)),
+           "mb4_set_state_device")
+
+
+def mb4_get_state_device(state, d_p, d_q) -> None:
+    _check(load_library().mb4_get_state_device(state, _dptr(d_p), _dptr(d_q)),
+           "mb4_get_state_device")
+
+
+def mb4_step(state, nsteps: int) -> int:
+    """Returns MB4_OK, or MB4_ENOCONV (not raised: the state stays valid)."""
+    rc = load_library().mb4_step(state, int(nsteps))
+    if rc not in (MB4_OK, MB4_ENOCONV):
+        _check(rc, "mb4_step")
+    return rc
+
+
+def mb4_energy(state) -> float:
+    h = c_double()
+    _check(load_library().mb4_energy(state, byref(h)), "mb4_energy")
+    return h.value
+
+
+def mb4_energy_components(state) -> dict:
+    out = (c_double * 6)()
+    _check(load_library().mb4_energy_components(state, out), "mb4_energy_components")
+    keys = ("H", "U_K", "U_I", "U_E", "prob", "participation")
+    return {k: out[i] for i, k in enumerate(keys)}
+
+
+def mb4_set_h(state, h: float) -> None:
+    _check(load_library().mb4_set_h(state, float(h)), "mb4_set_h")
+
+
+def mb4_steps_done(state) -> int:
+    return int(load_library().mb4_steps_done(state))
+
+
+def mb4_last_stats(state) -> dict:
+    it = c_int32()
+    sw = c_int32()
+    rn = c_double()
+    _check(load_library().mb4_last_stats(state, byref(it), byref(sw), byref(rn)),
+           "mb4_last_stats")
+    return {"newton_iters": it.value, "inner_sweeps": sw.value, "last_rnorm": rn.value}
+
+
+def mb4_newton_update(state, d_U, d_rbar, d_phibar) -> float:
+    rn = c_double()
+    rb = None if d_rbar is None else _dptr(d_rbar)
+    _check(load_library().mb4_newton_update(state, _dptr(d_U), rb, _dptr(d_phibar), byref(rn)),
+           "mb4_newton_update")
+    return rn.value
+
+
+def mb4_stage_solve(state, d_phibar, d_rbar, sweeps: int) -> None:
+    _check(load_library().mb4_stage_solve(state, _dptr(d_phibar), _dptr(d_rbar), int(sweeps)),
+           "mb4_stage_solve")
+
+
+class MB4State:
+    """Owning wrapper of one mb4_state (destroyed on close or garbage collection)."""
+
+    def __init__(self, nx: int, ny: int, potential, g: float, h: float, t_hop: float = 1.0,
+                 diag_shift: float = 0.0, eps: float = 0.0, max_newton: int = 0,
+                 inner_sweeps: int = 0, stream: int | None = None, mem_budget: int = 0):
+        self.nx, self.ny = int(nx), int(ny)
+        self.sites = self.nx * self.ny
+        opt = mb4_options_default()
+        if eps:
+            opt.eps = eps
+        if max_newton:
+            opt.max_newton = max_newton
+        if inner_sweeps:
+            opt.inner_sweeps = inner_sweeps
+        opt.stream = stream
+        opt.mem_budget = mem_budget
+        self._h = mb4_create(mb4_lattice(self.nx, self.ny, t_hop, diag_shift), potential,
+                             mb4_nonlinearity(g), h, opt)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_state(self, p, q) -> None:
+        mb4_set_state(self._h, p, q, self.sites)
+
+    def get_state(self) -> tuple[np.ndarray, np.ndarray]:
+        return mb4_get_state(self._h, self.sites)
+
+    def psi(self) -> np.ndarray:
+        p, q = self.get_state()
+        return p + 1j * q
+
+    def step(self, nsteps: int) -> int:
+        return mb4_step(self._h, nsteps)
+
+    def energy(self) -> float:
+        return mb4_energy(self._h)
+
+    def energy_components(self) -> dict:
+        return mb4_energy_components(self._h)
+
+    def set_h(self, h: float) -> None:
+        mb4_set_h(self._h, h)
+
+    def steps_done(self) -> int:
+        return mb4_steps_done(self._h)
+
+    def last_stats(self) -> dict:
+        return mb4_last_stats(self._h)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            mb4_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
