@@ -1,0 +1,213 @@
+"""Throughput benchmark of the MI355X MB4 integrator.
+
+One "step" is one MB4 time step (Algorithm 1 of Sakai et al., arXiv
+2003.04345): the first residual, the simplified Newton iterations with the
+three decoupled stage solves in one launch each, and the accepted update.
+Default workload: the 2048 x 2048 lattice (disorder W = 2, 0.1% defects at
++100, g = 2, sigma = 32 wavepacket, k = (pi/2, pi/4), h = 0.005), whose
+2000-step run is the HBM-bound configuration.  Inputs are generated on the
+host from seeds and uploaded before the timed region starts.
+
+Prints one JSON line with the throughput in lattice-site-steps/s, the energy
+drift of the run, a roofline entry for the kernel class that takes the most
+GPU time (algorithmic bytes per launch over its mean HIP-event duration,
+against MI355X's 8 TB/s), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import lattice_inputs as L  # noqa: E402
+
+METRIC = "lattice-site-steps/s (FP64 MB4) at energy drift≤1e-14"
+UNIT = "lattice-site-steps/s"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per lattice site of one launch of each kernel class:
+# what the kernel must read and write once, FP64, (p, q) = 16 B per field.
+#   first_residual:    u0 16 + V 8 -> Phibar 48
+#   stage_sweep_first: u0 16 + V 8 + Phibar 48 -> rbar 48
+#   stage_sweep:       u0 16 + V 8 + Phibar 48 + rbar 48 -> rbar 48
+#   update_residual:   u0 16 + V 8 + U 48 + rbar 48 -> U 48 + Phibar 48
+#                      (the first iteration starts from U = u0: no U read, 168)
+BYTES_PER_SITE = {
+    "first_residual": 72,
+    "stage_sweep_first": 120,
+    "stage_sweep": 168,
+    "update_residual": 216,
+}
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("mb4_kernels.hip", "mb4_internal.h", "mb4_constants.h"):
+        with open(os.path.join(ROOT, "paper_2003_04345_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, sites: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when there is none for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = data.get("kernels", {}).get(kernel)
+    if not entry or data.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return entry["bytes_per_site"] * sites
+
+
+def cpu_baseline(sample_side: int, sample_steps: int, workload: str) -> dict:
+    """The oracle as it stands, single-threaded, on a bounded sample of the
+    workload: the same potential and wavepacket recipe on a smaller lattice
+    (the oracle's cost per site-step barely depends on the lattice size)."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    base = L.CONFIGS[workload]
+    cfg = L.config(workload, nx=sample_side, ny=sample_side,
+                   defect_count=int(round(base.defect_count * sample_side ** 2 / base.sites)),
+                   steps=sample_steps)
+    v, p, q = L.make_inputs(cfg)
+    solver = "direct" if cfg.sites <= 64 * 64 else "gmres"
+    orc = O.oracle_for(cfg, v, solver=solver)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        t0 = time.perf_counter()
+        u = p + 1j * q
+        for _ in range(sample_steps):
+            u = orc.step(u)
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return {"value": cfg.sites * sample_steps / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": (f"{workload} recipe on a {sample_side}x{sample_side} lattice, "
+                       f"{sample_steps} steps, {solver} stage solves, 1 thread, "
+                       f"{dt:.1f} s")}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="lattice2048", choices=sorted(L.CONFIGS))
+    ap.add_argument("--eps", type=float, default=0.0, help="Newton tolerance (0: library default)")
+    ap.add_argument("--sweeps", type=int, default=0, help="block-Jacobi sweeps (0: default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-side", type=int, default=512)
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without per-kernel events (no roofline entry)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2003_04345_amd import mb4 as M
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    cfg = L.CONFIGS[args.workload]
+    steps = args.steps if args.steps is not None else cfg.steps
+    v, p, q = L.make_inputs(cfg)
+    st = M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, t_hop=cfg.t_hop, diag_shift=cfg.diag_shift,
+                    eps=args.eps, inner_sweeps=args.sweeps)
+    st.set_state(p, q)
+    h_start = st.energy()
+    if args.warmup:
+        rc = st.step(args.warmup)
+        if rc != M.MB4_OK:
+            raise RuntimeError(f"warmup failed: {M.error_detail()}")
+    if not args.no_profile:
+        st.profile_enable(True)
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk = max(1, steps // 20)
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        rc = st.step(n)
+        if rc != M.MB4_OK:
+            raise RuntimeError(f"step failed after {st.steps_done()} steps: {M.error_detail()}")
+        iters.append(st.last_stats()["newton_iters"])
+        done += n
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = st.profile_read() if not args.no_profile else {}
+    h_end = st.energy()
+    drift = abs(h_end - h_start) / abs(h_start)
+    stats = st.last_stats()
+    st.close()
+
+    sites = cfg.sites
+    result = {
+        "metric": METRIC,
+        "value": sites * steps / elapsed,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded disorder, defects and Gaussian wavepacket)",
+        "config": {"workload": cfg.name, "nx": cfg.nx, "ny": cfg.ny, "h": cfg.h, "g": cfg.g,
+                   "disorder_w": cfg.disorder_w, "defects": cfg.defect_count,
+                   "defect_v": cfg.defect_v, "sigma": cfg.sigma, "seed": cfg.seed,
+                   "parallelism": "single GPU"},
+        "energy_drift": drift,
+        "energy_drift_ok": drift <= 1e-14,
+        "newton_iters_last": stats["newton_iters"],
+        "inner_sweeps_per_solve": stats["inner_sweeps"] // max(stats["newton_iters"], 1),
+    }
+    if prof:
+        dominant = max(prof, key=lambda k: prof[k][1])
+        n_launch, total_ms = prof[dominant]
+        per_launch_s = total_ms / 1e3 / max(n_launch, 1)
+        bytes_launch = BYTES_PER_SITE[dominant] * sites
+        achieved = bytes_launch / per_launch_s / 1e9
+        traffic = measured_traffic(dominant, sites)
+        result["roofline"] = {
+            "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": bytes_launch, "mean_launch_us": per_launch_s * 1e6,
+        }
+        result["kernel_time_ms"] = {k: {"launches": n, "total_ms": ms} for k, (n, ms) in prof.items()}
+        gpu_ms = sum(ms for _, ms in prof.values())
+        result["kernel_time_fraction_of_wall"] = gpu_ms / (elapsed * 1e3)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_side, args.cpu_sample_steps,
+                                              args.workload)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -149,6 +149,24 @@ MB4_API int64_t mb4_steps_done(const mb4_state* state);
 MB4_API int mb4_last_stats(const mb4_state* state, int32_t* newton_iters,
                    int32_t* inner_sweeps, double* last_rnorm);
 
+/* ||r^l||_inf of the Newton updates l = 1 .. n of the last accepted step into
+ * out[0 .. n-1] (Algorithm 1, convergence measure r); *count receives
+ * min(n, iterations).  out may be NULL when n == 0. */
+MB4_API int mb4_last_residuals(const mb4_state* state, double* out, int32_t n,
+                               int32_t* count);
+
+/* Per-kernel timing for measurement (the per-phase breakdown of Sec. 3.2).
+ * While enabled, each kernel launch of mb4_step is bracketed by HIP events on
+ * the state's stream and its duration is added to its kernel class; launches
+ * of Newton iterations after convergence (which return at once) are not
+ * counted.  Enabling resets the accumulators.  Classes are numbered
+ * 0 .. mb4_profile_classes()-1; mb4_profile_name gives a static name. */
+MB4_API int mb4_profile_enable(mb4_state* state, int32_t enable);
+MB4_API int32_t mb4_profile_classes(void);
+MB4_API const char* mb4_profile_name(int32_t kernel_class);
+MB4_API int mb4_profile_read(const mb4_state* state, int32_t kernel_class,
+                             int64_t* launches, double* total_ms);
+
 /* Kernel-level entry points, for callers that drive the Newton loop
  * themselves and for testing each kernel against a reference.  Stage fields
  * are three stage-major planes of nx*ny sites, each site an interleaved

@@ -44,13 +44,19 @@ struct ConvCheck {
   double eps;
 };
 
+// Optional timestamps of one launch (both NULL: untimed).
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
 // Kernel launchers (each enqueues on `stream`; return hipSuccess or an error).
 hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream);
 
 // Transformed residual at U = e_3 (x) u_0: phib_i = -h TC_i f(u_0); records
 // ||u_0||_inf.
 hipError_t launch_first_residual(const Lattice& lat, Planes3 phib, Stats* stats,
-                                 hipStream_t stream);
+                                 hipStream_t stream, LaunchEvents ev = {});
 
 // Uout <- base + (T (x) I) rbar (base = Uin, or e_3 (x) u_0 if from_u0), then
 // phib <- (T^-1 (x) I) Phi(Uout); ||(T (x) I) rbar||_inf goes to *rslot (if
@@ -59,13 +65,14 @@ hipError_t launch_first_residual(const Lattice& lat, Planes3 phib, Stats* stats,
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                                   bool has_rbar, bool from_u0, Planes3 phib,
                                   unsigned long long* rslot, ConvCheck check,
-                                  hipStream_t stream);
+                                  hipStream_t stream, LaunchEvents ev = {});
 
 // One block-Jacobi sweep for the three stage systems (I - h lambda_i J) r_i
 // = -phib_i; first == true starts from r = 0 (rin ignored).  rin and rout
 // must not alias.
 hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
-                              bool first, ConvCheck check, hipStream_t stream);
+                              bool first, ConvCheck check, hipStream_t stream,
+                              LaunchEvents ev = {});
 
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -19,6 +19,7 @@
 // block, four wave64s); the block -> tile map is XCD-aware so that the tiles
 // one XCD works on are contiguous and share halo rows in its L2.
 #include <float.h>
+#include <hip/hip_ext.h>
 
 #include "mb4_constants.h"
 #include "mb4_internal.h"
@@ -81,7 +82,13 @@ __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long
     unsigned long long m = red[0];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) m = umax(m, red[w]);
-    atomicMax(slot, m);
+    // Device-scope atomics on one address serialise across the XCDs; most
+    // blocks hold a value below the running maximum, so read it first (a
+    // coherent load) and only post a larger value.  The slot only grows, so a
+    // block that skips has v <= what the slot already holds.
+    const unsigned long long cur =
+        __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (m > cur) atomicMax(slot, m);
   }
 }
 
@@ -435,58 +442,62 @@ int tile_blocks(int nx, int ny) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Every launch goes through hipExtLaunchKernelGGL so that, when the runtime
+// asks for timing, the start/stop timestamps are taken by the dispatch itself
+// (no extra marker packets between kernels).
+#define MB4_LAUNCH(kernel, grid, block, ev, ...)                                             \
+  do {                                                                                       \
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, (ev).start, (ev).stop, 0u,        \
+                          __VA_ARGS__);                                                      \
+    return hipGetLastError();                                                                \
+  } while (0)
+
 hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream) {
-  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, stream, stats, upto);
-  return hipGetLastError();
+  MB4_LAUNCH(k_reset_stats, dim3(1), dim3(64), LaunchEvents{}, stats, upto);
 }
 
 hipError_t launch_first_residual(const Lattice& lat, Planes3 phib, Stats* stats,
-                                 hipStream_t stream) {
-  hipLaunchKernelGGL(k_first_residual, dim3(tile_blocks(lat.nx, lat.ny)), dim3(kTile), 0, stream,
-                     lat, phib, stats);
-  return hipGetLastError();
+                                 hipStream_t stream, LaunchEvents ev) {
+  MB4_LAUNCH(k_first_residual, dim3(tile_blocks(lat.nx, lat.ny)), dim3(kTile), ev, lat, phib,
+             stats);
 }
 
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                                   bool has_rbar, bool from_u0, Planes3 phib,
-                                  unsigned long long* rslot, ConvCheck check,
-                                  hipStream_t stream) {
+                                  unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                                  LaunchEvents ev) {
   const dim3 grid(tile_blocks(lat.nx, lat.ny)), block(kTile);
   if (from_u0 && has_rbar)
-    hipLaunchKernelGGL((k_update_residual<true, true>), grid, block, 0, stream, lat, Uin, Uout,
-                       rbar, phib, rslot, check);
+    MB4_LAUNCH((k_update_residual<true, true>), grid, block, ev, lat, Uin, Uout, rbar, phib,
+               rslot, check);
   else if (from_u0)
-    hipLaunchKernelGGL((k_update_residual<true, false>), grid, block, 0, stream, lat, Uin, Uout,
-                       rbar, phib, rslot, check);
+    MB4_LAUNCH((k_update_residual<true, false>), grid, block, ev, lat, Uin, Uout, rbar, phib,
+               rslot, check);
   else if (has_rbar)
-    hipLaunchKernelGGL((k_update_residual<false, true>), grid, block, 0, stream, lat, Uin, Uout,
-                       rbar, phib, rslot, check);
+    MB4_LAUNCH((k_update_residual<false, true>), grid, block, ev, lat, Uin, Uout, rbar, phib,
+               rslot, check);
   else
-    hipLaunchKernelGGL((k_update_residual<false, false>), grid, block, 0, stream, lat, Uin, Uout,
-                       rbar, phib, rslot, check);
-  return hipGetLastError();
+    MB4_LAUNCH((k_update_residual<false, false>), grid, block, ev, lat, Uin, Uout, rbar, phib,
+               rslot, check);
 }
 
 hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
-                              bool first, ConvCheck check, hipStream_t stream) {
+                              bool first, ConvCheck check, hipStream_t stream, LaunchEvents ev) {
   const dim3 grid(tile_blocks(lat.nx, lat.ny)), block(kTile);
   if (first)
-    hipLaunchKernelGGL(k_stage_sweep<true>, grid, block, 0, stream, lat, phib, rin, rout, check);
+    MB4_LAUNCH(k_stage_sweep<true>, grid, block, ev, lat, phib, rin, rout, check);
   else
-    hipLaunchKernelGGL(k_stage_sweep<false>, grid, block, 0, stream, lat, phib, rin, rout, check);
-  return hipGetLastError();
+    MB4_LAUNCH(k_stage_sweep<false>, grid, block, ev, lat, phib, rin, rout, check);
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_interleave, dim3((n + 255) / 256), dim3(256), 0, stream, p, q, out, n);
-  return hipGetLastError();
+  MB4_LAUNCH(k_interleave, dim3((n + 255) / 256), dim3(256), LaunchEvents{}, p, q, out, n);
 }
 
 hipError_t launch_deinterleave(const double2* in, double* p, double* q, int n,
                                hipStream_t stream) {
-  hipLaunchKernelGGL(k_deinterleave, dim3((n + 255) / 256), dim3(256), 0, stream, in, p, q, n);
-  return hipGetLastError();
+  MB4_LAUNCH(k_deinterleave, dim3((n + 255) / 256), dim3(256), LaunchEvents{}, in, p, q, n);
 }
 
 size_t energy_partials_count(int nx, int ny) {
@@ -495,10 +506,12 @@ size_t energy_partials_count(int nx, int ny) {
 
 hipError_t launch_energy(const Lattice& lat, double* partials, double* out, hipStream_t stream) {
   const int nb = tile_blocks(lat.nx, lat.ny);
-  hipLaunchKernelGGL(k_energy_partial, dim3(nb), dim3(kTile), 0, stream, lat, partials);
+  hipExtLaunchKernelGGL(k_energy_partial, dim3(nb), dim3(kTile), 0, stream, nullptr, nullptr, 0u,
+                        lat, partials);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kTile), 0, stream, partials, nb, out);
+  hipExtLaunchKernelGGL(k_energy_final, dim3(1), dim3(kTile), 0, stream, nullptr, nullptr, 0u,
+                        static_cast<const double*>(partials), nb, out);
   return hipGetLastError();
 }
 

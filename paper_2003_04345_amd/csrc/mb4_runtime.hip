@@ -97,6 +97,18 @@ struct mb4_state {
   double* partials = nullptr;
   double* eout = nullptr;
   double* h_eout = nullptr;  // pinned, 6 doubles
+  // Per-kernel timing (mb4_profile_*): events bracketing launches of the
+  // current step, collected once the step is decided.
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec {
+    int cls, iter;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> prof_pending;
+  int64_t prof_launches[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0, 0, 0, 0};
   int64_t steps_done = 0;
   int last_iters = 0;
   int last_sweeps = 0;
@@ -135,6 +147,8 @@ int halloc(mb4_state* s, void** p, size_t bytes) {
 }
 
 void free_all(mb4_state* s) {
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  s->ev_pool.clear();
   for (void* p : s->device_allocs) (void)hipFree(p);
   for (void* p : s->host_allocs) (void)hipHostFree(p);
   s->device_allocs.clear();
@@ -172,15 +186,67 @@ int use_device(const mb4_state* s) {
   return MB4_OK;
 }
 
+enum KernelClass { kFirstResidual = 0, kSweepFirst = 1, kSweep = 2, kUpdateResidual = 3 };
+constexpr int kKernelClasses = 4;
+const char* const kKernelNames[kKernelClasses] = {"first_residual", "stage_sweep_first",
+                                                  "stage_sweep", "update_residual"};
+
+int prof_event(mb4_state* s, hipEvent_t* ev) {
+  if (s->ev_used == s->ev_pool.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    s->ev_pool.push_back(e);
+  }
+  *ev = s->ev_pool[s->ev_used++];
+  return MB4_OK;
+}
+
+// Adds the durations of the recorded launches of iterations <= last_iter
+// (iteration 0: the first residual) to the per-class totals.
+int prof_collect(mb4_state* s, int last_iter) {
+  for (const auto& r : s->prof_pending) {
+    if (r.iter > last_iter) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    s->prof_launches[r.cls] += 1;
+    s->prof_ms[r.cls] += ms;
+  }
+  s->prof_pending.clear();
+  s->ev_used = 0;
+  return MB4_OK;
+}
+
+// Events for one launch: a fresh pair from the pool when profiling (the
+// launch records its own start/stop timestamps), none otherwise.
+int launch_events(mb4_state* s, int cls, int iter, mb4::LaunchEvents* ev) {
+  *ev = mb4::LaunchEvents{};
+  if (!s->prof_on) return MB4_OK;
+  int rc = prof_event(s, &ev->start);
+  if (rc == MB4_OK) rc = prof_event(s, &ev->stop);
+  if (rc != MB4_OK) return rc;
+  s->prof_pending.push_back(mb4_state::Rec{cls, iter, ev->start, ev->stop});
+  return MB4_OK;
+}
+
+// Enqueues one kernel launch; `expr` may use the LaunchEvents `ev_`.
+#define LAUNCH(s, cls, iter, expr)                        \
+  do {                                                    \
+    mb4::LaunchEvents ev_;                                \
+    const int rc_ = launch_events((s), (cls), (iter), &ev_); \
+    if (rc_ != MB4_OK) return rc_;                        \
+    HIP_TRY(expr);                                        \
+  } while (0)
+
 // Enqueues the stage solve of one Newton iteration: `sweeps` block-Jacobi
 // sweeps from r = 0 alternating between ra and rb; returns the planes that
 // hold the result.
-int enqueue_solve(mb4_state* s, const Lattice& L, CPlanes3 phib, ConvCheck chk,
+int enqueue_solve(mb4_state* s, const Lattice& L, CPlanes3 phib, ConvCheck chk, int iter,
                   double2* const** result) {
   for (int k = 0; k < s->sweeps; ++k) {
     double2* const(&out)[3] = (k % 2 == 0) ? s->ra : s->rb;
     double2* const(&in)[3] = (k % 2 == 0) ? s->rb : s->ra;
-    HIP_TRY(mb4::launch_stage_sweep(L, phib, C(in), P(out), k == 0, chk, s->stream));
+    LAUNCH(s, k == 0 ? kSweepFirst : kSweep, iter,
+           mb4::launch_stage_sweep(L, phib, C(in), P(out), k == 0, chk, s->stream, ev_));
   }
   *result = ((s->sweeps - 1) % 2 == 0) ? s->ra : s->rb;
   return MB4_OK;
@@ -190,7 +256,8 @@ int enqueue_solve(mb4_state* s, const Lattice& L, CPlanes3 phib, ConvCheck chk,
 int step_once(mb4_state* s) {
   const Lattice L = lattice_of(s);
   HIP_TRY(mb4::launch_reset_stats(s->stats, s->max_newton, s->stream));
-  HIP_TRY(mb4::launch_first_residual(L, P(s->phib), s->stats, s->stream));
+  LAUNCH(s, kFirstResidual, 0,
+         mb4::launch_first_residual(L, P(s->phib), s->stats, s->stream, ev_));
   int done = 0;
   int batch = std::max(1, std::min(s->predicted, s->max_newton));
   for (;;) {
@@ -199,14 +266,15 @@ int step_once(mb4_state* s) {
       const ConvCheck chk = (l >= 2) ? ConvCheck{s->stats, l - 1, s->eps}
                                      : ConvCheck{nullptr, 0, 0.0};
       double2* const* rfin = nullptr;
-      int rc = enqueue_solve(s, L, C(s->phib), chk, &rfin);
+      int rc = enqueue_solve(s, L, C(s->phib), chk, l, &rfin);
       if (rc != MB4_OK) return rc;
       // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
       double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
       double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
       const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
-      HIP_TRY(mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
-                                          &s->stats->rmax[l], chk, s->stream));
+      LAUNCH(s, kUpdateResidual, l,
+             mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
+                                         &s->stats->rmax[l], chk, s->stream, ev_));
     }
     HIP_TRY(hipMemcpyAsync(s->h_stats, s->stats, sizeof(unsigned long long) * (upto + 2),
                            hipMemcpyDeviceToHost, s->stream));
@@ -222,14 +290,18 @@ int step_once(mb4_state* s) {
         s->last_sweeps = l * s->sweeps;
         s->last_rnorm = r;
         s->predicted = l;
-        return MB4_OK;
+        return prof_collect(s, l);
       }
-      if (!isfinite(r))
+      if (!isfinite(r)) {
+        (void)prof_collect(s, upto);
         return fail(MB4_ENOCONV, "non-finite Newton update at iteration %d", l);
+      }
     }
-    if (upto >= s->max_newton)
+    if (upto >= s->max_newton) {
+      (void)prof_collect(s, upto);
       return fail(MB4_ENOCONV, "no convergence in %d Newton iterations (||r||_inf = %.3e, tol %.3e)",
                   s->max_newton, bits_to_double(s->h_stats[1 + upto]), tol);
+    }
     done = upto;
     batch = 1;
   }
@@ -463,6 +535,44 @@ int mb4_last_stats(const mb4_state* s, int32_t* newton_iters, int32_t* inner_swe
   if (newton_iters) *newton_iters = s->last_iters;
   if (inner_sweeps) *inner_sweeps = s->last_sweeps;
   if (last_rnorm) *last_rnorm = s->last_rnorm;
+  return MB4_OK;
+}
+
+int mb4_last_residuals(const mb4_state* s, double* out, int32_t n, int32_t* count) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (n < 0 || (n > 0 && out == nullptr)) return fail(MB4_EINVAL, "bad output buffer");
+  const int m = std::min(n, s->last_iters);
+  for (int l = 1; l <= m; ++l) out[l - 1] = bits_to_double(s->h_stats[1 + l]);
+  if (count) *count = m;
+  return MB4_OK;
+}
+
+int mb4_profile_enable(mb4_state* s, int32_t enable) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  s->prof_on = enable != 0;
+  s->prof_pending.clear();
+  s->ev_used = 0;
+  for (int k = 0; k < kKernelClasses; ++k) {
+    s->prof_launches[k] = 0;
+    s->prof_ms[k] = 0.0;
+  }
+  return MB4_OK;
+}
+
+int32_t mb4_profile_classes(void) { return kKernelClasses; }
+
+const char* mb4_profile_name(int32_t cls) {
+  return (cls >= 0 && cls < kKernelClasses) ? kKernelNames[cls] : "";
+}
+
+int mb4_profile_read(const mb4_state* s, int32_t cls, int64_t* launches, double* total_ms) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (cls < 0 || cls >= kKernelClasses) return fail(MB4_EINVAL, "no kernel class %d", cls);
+  if (launches) *launches = s->prof_launches[cls];
+  if (total_ms) *total_ms = s->prof_ms[cls];
   return MB4_OK;
 }
 

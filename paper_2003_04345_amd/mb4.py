@@ -61,6 +61,11 @@ _SIGNATURES = {
     "mb4_last_stats": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]),
     "mb4_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
     "mb4_stage_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_int32]),
+    "mb4_last_residuals": (c_int, [c_void_p, POINTER(c_double), c_int32, POINTER(c_int32)]),
+    "mb4_profile_enable": (c_int, [c_void_p, c_int32]),
+    "mb4_profile_classes": (c_int32, []),
+    "mb4_profile_name": (c_char_p, [c_int32]),
+    "mb4_profile_read": (c_int, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "mb4_strerror": (c_char_p, [c_int]),
     "mb4_error_detail": (c_char_p, []),
 }
@@ -196,6 +201,30 @@ def mb4_last_stats(state) -> dict:
     return {"newton_iters": it.value, "inner_sweeps": sw.value, "last_rnorm": rn.value}
 
 
+def mb4_last_residuals(state, n: int = 1000) -> list[float]:
+    out = (c_double * max(n, 1))()
+    cnt = c_int32()
+    _check(load_library().mb4_last_residuals(state, out, int(n), byref(cnt)),
+           "mb4_last_residuals")
+    return [out[i] for i in range(cnt.value)]
+
+
+def mb4_profile_enable(state, enable: bool = True) -> None:
+    _check(load_library().mb4_profile_enable(state, 1 if enable else 0), "mb4_profile_enable")
+
+
+def mb4_profile_read(state) -> dict:
+    """{kernel name: (launches, total milliseconds)} since profiling was enabled."""
+    lib = load_library()
+    out = {}
+    for k in range(lib.mb4_profile_classes()):
+        n = c_int64()
+        ms = c_double()
+        _check(lib.mb4_profile_read(state, k, byref(n), byref(ms)), "mb4_profile_read")
+        out[lib.mb4_profile_name(k).decode()] = (n.value, ms.value)
+    return out
+
+
 def mb4_newton_update(state, d_U, d_rbar, d_phibar) -> float:
     rn = c_double()
     rb = None if d_rbar is None else _dptr(d_rbar)
@@ -260,6 +289,15 @@ class MB4State:
 
     def last_stats(self) -> dict:
         return mb4_last_stats(self._h)
+
+    def last_residuals(self) -> list[float]:
+        return mb4_last_residuals(self._h)
+
+    def profile_enable(self, enable: bool = True) -> None:
+        mb4_profile_enable(self._h, enable)
+
+    def profile_read(self) -> dict:
+        return mb4_profile_read(self._h)
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

@@ -1,0 +1,81 @@
+"""Writes the stored oracle results that the GPU parity tests compare with.
+
+Runs only the CPU oracle (oracle/) on the seeded workloads of lattice_inputs;
+nothing here touches the GPU library.  Usage:
+    python tests/golden/make_golden.py [lattice32] [lattice256] [lattice2048]
+
+Each JSON file holds the workload name, the number of steps, the Newton
+tolerance, the oracle's stage solver, the site indices compared (all sites,
+or a fixed sample for the large lattices), Re/Im of psi there after the run,
+the energies logged along the run and the oracle's Newton iteration counts.
+Floats are stored with repr, which round-trips exactly.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import lattice_inputs as L  # noqa: E402
+import oracle as O  # noqa: E402
+
+CASES = {
+    # name: (steps, eps, solver, energy_every, sampled)
+    "lattice32": (1000, 1e-14, "direct", 100, False),
+    "lattice256": (20, 1e-14, "gmres", 10, True),
+    "lattice2048": (2, 1e-14, "gmres", 1, True),
+}
+
+
+def sample_sites(cfg, n_packet=512, n_uniform=512, seed=2024):
+    """Half of the sample inside three packet widths of the centre, half
+    uniform over the lattice; fixed by the seed."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(cfg.nx)
+    y = np.arange(cfg.ny)
+    dx = np.abs(x - cfg.nx // 2)
+    dx = np.minimum(dx, cfg.nx - dx)
+    dy = np.abs(y - cfg.ny // 2)
+    dy = np.minimum(dy, cfg.ny - dy)
+    d2 = (dy[:, None] ** 2 + dx[None, :] ** 2).reshape(-1)
+    near = np.flatnonzero(d2 <= (3 * cfg.sigma) ** 2)
+    a = rng.choice(near, size=min(n_packet, near.size), replace=False)
+    b = rng.choice(cfg.sites, size=n_uniform, replace=False)
+    return np.unique(np.concatenate([a, b]))
+
+
+def make(name: str) -> str:
+    steps, eps, solver, every, sampled = CASES[name]
+    cfg = L.CONFIGS[name]
+    v, p, q = L.make_inputs(cfg)
+    orc = O.oracle_for(cfg, v, eps=eps, solver=solver)
+    t0 = time.time()
+    u, energies = orc.run(p + 1j * q, steps, energy_every=every)
+    dt = time.time() - t0
+    sites = sample_sites(cfg) if sampled else np.arange(cfg.sites)
+    out = {
+        "workload": name, "steps": steps, "eps": eps, "solver": solver,
+        "generated_by": "tests/golden/make_golden.py (CPU oracle only)",
+        "oracle_seconds": round(dt, 1),
+        "sites": [int(s) for s in sites],
+        "p": [repr(float(x)) for x in u.real[sites]],
+        "q": [repr(float(x)) for x in u.imag[sites]],
+        "energies": [[int(n), repr(float(e))] for n, e in energies],
+        "newton_iterations": orc.iteration_log,
+    }
+    path = os.path.join(HERE, f"{name}_oracle.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, separators=(",", ":"))
+    return path
+
+
+if __name__ == "__main__":
+    for nm in (sys.argv[1:] or list(CASES)):
+        print(nm, make(nm), flush=True)
