@@ -34,16 +34,20 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per lattice site of one launch of each kernel class:
 # what the kernel must read and write once, FP64, (p, q) = 16 B per field.
-#   first_residual:    u0 16 + V 8 -> Phibar 48
-#   stage_sweep_first: u0 16 + V 8 + Phibar 48 -> rbar 48
-#   stage_sweep:       u0 16 + V 8 + Phibar 48 + rbar 48 -> rbar 48
-#   update_residual:   u0 16 + V 8 + U 48 + rbar 48 -> U 48 + Phibar 48
-#                      (the first iteration starts from U = u0: no U read, 168)
+#   stage_solve_first:     u0 16 + V 8 -> rbar 48 (the residual at U = u0 is
+#                          built in place from u0 and its neighbours)
+#   stage_solve:           u0 16 + V 8 + Phibar 48 -> rbar 48 (all fused sweeps)
+#   stage_sweep:           u0 16 + V 8 + Phibar 48 + rbar 48 -> rbar 48
+#   update_residual_first: u0 16 + V 8 + rbar 48 -> U 48 + Phibar 48
+#   update_residual:       u0 16 + V 8 + U 48 + rbar 48 -> U 48 + Phibar 48
+#   final_update:          U_3 16 + rbar 48 -> u0 16
 BYTES_PER_SITE = {
-    "first_residual": 72,
-    "stage_sweep_first": 120,
+    "stage_solve_first": 72,
+    "stage_solve": 120,
     "stage_sweep": 168,
+    "update_residual_first": 168,
     "update_residual": 216,
+    "final_update": 80,
 }
 
 

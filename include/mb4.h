@@ -79,7 +79,7 @@ typedef struct {
   double eps;            /* Newton tolerance relative to ||u_0||_inf; default 1e-13
                             (the paper's epsilon, Sec. 3, read as relative) */
   int32_t max_newton;    /* Newton iterations before MB4_ENOCONV; default 50, <= 1000 */
-  int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve; default 4, <= 64 */
+  int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve; default 3, <= 64 */
   void* stream;          /* hipStream_t for all work of the state; NULL = null stream */
   uint64_t mem_budget;   /* bytes of device memory the state may allocate; 0 = no limit */
 } mb4_options;

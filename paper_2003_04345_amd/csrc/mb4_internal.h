@@ -36,11 +36,13 @@ struct CPlanes3 {
   const double2* s[3];
 };
 
-// Early-exit test shared by all kernels of Newton iteration l >= 2: the
-// iteration is skipped once ||r^{l-1}||_inf <= eps * max(||u_0||_inf, tiny).
+// Convergence test of Newton iteration `prev`:
+// ||r^prev||_inf <= eps * max(||u_0||_inf, DBL_MIN).  Kernels of iteration l
+// return at once when iteration l-1 passed it; the update pass of iteration l
+// turns into the final update when iteration l passed it.
 struct ConvCheck {
-  const Stats* stats;  // NULL: never skip
-  int prev;            // index of the iteration whose norm decides
+  const Stats* stats;  // NULL: the test is false
+  int prev;            // iteration whose norm decides
   double eps;
 };
 
@@ -53,26 +55,44 @@ struct LaunchEvents {
 // Kernel launchers (each enqueues on `stream`; return hipSuccess or an error).
 hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream);
 
-// Transformed residual at U = e_3 (x) u_0: phib_i = -h TC_i f(u_0); records
-// ||u_0||_inf.
-hipError_t launch_first_residual(const Lattice& lat, Planes3 phib, Stats* stats,
-                                 hipStream_t stream, LaunchEvents ev = {});
+// Newton iteration 1, stage solve: `sweeps` (1..4) block-Jacobi sweeps of
+// (I - h lambda_i J) r_i = -Phibar_i with Phibar_i = -h TC_i f(u_0) (the
+// residual at U^0 = e_3 (x) u_0) built in place, into rout.  Records
+// ||u_0||_inf in first->u0max and ||(T (x) I) r||_inf in *rslot (if not
+// NULL), clears `next` (if not NULL) up to rmax[next_upto], and writes that
+// Phibar to phib_out when phib_out.s[0] is not NULL.
+hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
+                              unsigned long long* rslot, Stats* first, Stats* next,
+                              int next_upto, Planes3 phib_out, hipStream_t stream,
+                              LaunchEvents ev = {});
 
+// Newton iteration l >= 2 (or a kernel-level call), stage solve: `sweeps`
+// (1..4) block-Jacobi sweeps from r = 0 for the three stage systems
+// (I - h lambda_i J) r_i = -phib_i in one temporally blocked pass;
+// ||(T (x) I) r||_inf to *rslot if not NULL.
+constexpr int kMaxFusedSweeps = 4;
+hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, int sweeps,
+                              unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                              LaunchEvents ev = {});
+
+// One more block-Jacobi sweep from the iterate rin (rin and rout must not
+// alias); ||(T (x) I) rout||_inf to *rslot if not NULL.
+hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
+                              unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                              LaunchEvents ev = {});
+
+// Update pass of one Newton iteration.  Skipped when `check` says an earlier
+// iteration converged.  If `fin` says this iteration converged (its norm was
+// recorded by the stage solve): u0_out <- U_3 + (T rbar)_3 (base U_3 = Uin[2],
+// or u_0 if from_u0), site by site, and nothing else.  Otherwise:
 // Uout <- base + (T (x) I) rbar (base = Uin, or e_3 (x) u_0 if from_u0), then
-// phib <- (T^-1 (x) I) Phi(Uout); ||(T (x) I) rbar||_inf goes to *rslot (if
-// not NULL).  Uin and Uout must not alias: blocks read the halo of Uin while
-// others write Uout.  Uout is not written when !from_u0 && !has_rbar.
+// phib <- (T^-1 (x) I) Phi(Uout); ||(T (x) I) rbar||_inf goes to *rslot if not
+// NULL.  Uin and Uout must not alias (blocks read the halo of Uin while
+// others write Uout).  Uout is not written when !from_u0 && !has_rbar.
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                                   bool has_rbar, bool from_u0, Planes3 phib,
-                                  unsigned long long* rslot, ConvCheck check,
-                                  hipStream_t stream, LaunchEvents ev = {});
-
-// One block-Jacobi sweep for the three stage systems (I - h lambda_i J) r_i
-// = -phib_i; first == true starts from r = 0 (rin ignored).  rin and rout
-// must not alias.
-hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
-                              bool first, ConvCheck check, hipStream_t stream,
-                              LaunchEvents ev = {});
+                                  unsigned long long* rslot, ConvCheck check, ConvCheck fin,
+                                  double2* u0_out, hipStream_t stream, LaunchEvents ev = {});
 
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -1,23 +1,29 @@
 // HIP kernels of one MB4 step on the periodic 2D lattice (gfx950, FP64).
 //
-// Method: Sakai et al., arXiv 2003.04345, Sec. 2.2-2.3 and Algorithm 1.
-//  * k_first_residual:  transformed residual at the initial guess
-//    U^0 = e_3 (x) u_0 (Algorithm 1, Newton loop entry).
-//  * k_update_residual: U <- U + (T (x) I) rbar (Eq. MB4_6 and the update of
-//    Eq. Newton1), the stage combinations and S grad H at the Gauss-Legendre
-//    nodes (Eqs. Lagrange, fKu2, fIu2), Phi (Eq. Phidefinition), the
-//    transform Phibar = (T^-1 (x) I) Phi (Eq. MB4_4) and ||r||_inf, in one
-//    pass over LDS tiles with a one-site halo.
-//  * k_stage_sweep: one block-Jacobi sweep for all three decoupled stage
-//    systems (I - h lambda_i J) rbar_i = -Phibar_i (Eq. MB4_5) at once, with
-//    J frozen at u_0 (Eqs. Jacobianall, JL, JR).
+// Method: Sakai et al., arXiv 2003.04345, Sec. 2.2-2.3 and Algorithm 1.  One
+// Newton iteration l is two passes over HBM:
+//  * k_stage_solve: the three decoupled stage systems
+//    (I - h lambda_i J) rbar_i = -Phibar_i (Eq. MB4_5), J frozen at u_0
+//    (Eqs. Jacobianall, JL, JR), all three stages at once, by up to four
+//    block-Jacobi sweeps temporally blocked in LDS; it also reduces
+//    ||r||_inf = ||(T (x) I) rbar||_inf, the convergence measure of
+//    Algorithm 1.  In iteration 1 it builds Phibar itself from u_0: at
+//    U^0 = e_3 (x) u_0 the residual is Phi_m = -h c_m f(u_0).
+//  * k_update_residual: if ||r^l||_inf met the tolerance, the accepted value
+//    u_1 = U_{c_3} = U_3 + (T rbar)_3 is written over u_0 (Sec. 2.2: c_3 = 1)
+//    and the step is done; otherwise U <- U + (T (x) I) rbar (Eqs. MB4_6,
+//    Newton1), the stage combinations and S grad H at the Gauss-Legendre
+//    nodes (Eqs. Lagrange, fKu2, fIu2), Phi (Eq. Phidefinition) and
+//    Phibar = (T^-1 (x) I) Phi (Eq. MB4_4), over LDS tiles with a one-site
+//    halo.
+//  * k_stage_sweep: one more sweep, for solves that ask for more than four.
 //  * k_energy_*: H and its parts (Sec. 2.1) by a fixed-order double-double
 //    reduction.
 //
 // Layout: every field is an array of double2 (p, q) per site, site = y*nx+x;
-// a stage field is three such planes.  Tiles of 64 x 4 sites (one 256-thread
-// block, four wave64s); the block -> tile map is XCD-aware so that the tiles
-// one XCD works on are contiguous and share halo rows in its L2.
+// a stage field is three such planes.  Block -> tile maps are XCD-aware so
+// that the tiles one XCD works on are contiguous and share halo rows in its
+// L2.
 #include <float.h>
 #include <hip/hip_ext.h>
 
@@ -30,9 +36,8 @@ namespace {
 constexpr int kTX = 64;
 constexpr int kTY = 4;
 constexpr int kTile = kTX * kTY;
-constexpr int kWaves = kTile / 64;
 constexpr int kXcds = 8;
-constexpr int kRing = 2 * (kTX + 2) + 2 * kTY;   // halo positions of a tile
+constexpr int kRing = 2 * (kTX + 2) + 2 * kTY;   // halo positions of a residual tile
 static_assert(kRing <= kTile, "halo ring must fit one pass of the block");
 
 __device__ __forceinline__ int wrap(int v, int n) {
@@ -59,33 +64,40 @@ __device__ __forceinline__ unsigned long long umax(unsigned long long a, unsigne
   return a > b ? a : b;
 }
 
+__device__ __forceinline__ double bits_double(unsigned long long b) {
+  return __longlong_as_double(static_cast<long long>(b));
+}
+
 __device__ __forceinline__ double conv_tol(double eps, double u0max) {
   return eps * (u0max > DBL_MIN ? u0max : DBL_MIN);
 }
 
-__device__ __forceinline__ bool skip_iteration(const ConvCheck& c) {
+// True when Newton iteration c.prev (>= 1) already met the tolerance.
+__device__ __forceinline__ bool converged_at(const ConvCheck& c) {
   if (c.stats == nullptr) return false;
-  const double u0max = __longlong_as_double(static_cast<long long>(c.stats->u0max));
-  const double r = __longlong_as_double(static_cast<long long>(c.stats->rmax[c.prev]));
+  const double u0max = bits_double(c.stats->u0max);
+  const double r = bits_double(c.stats->rmax[c.prev]);
   return r <= conv_tol(c.eps, u0max);
 }
 
-// Block-wide max of v, then one atomic per block.
+// Block-wide max of v posted to *slot.  Device-scope atomics on one address
+// serialise across the XCDs; most blocks hold a value below the running
+// maximum, so thread 0 reads it first (a coherent load) and only posts a
+// larger value.  The slot only grows, so a block that skips has v <= what
+// the slot already holds.
+template <int NT>
 __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long* slot) {
-  __shared__ unsigned long long red[kWaves];
+  constexpr int kW = NT / 64;
+  __shared__ unsigned long long red[kW];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = umax(v, __shfl_xor(v, off, 64));
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();  // red[] may still be read by a previous reduction
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long m = red[0];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) m = umax(m, red[w]);
-    // Device-scope atomics on one address serialise across the XCDs; most
-    // blocks hold a value below the running maximum, so read it first (a
-    // coherent load) and only post a larger value.  The slot only grows, so a
-    // block that skips has v <= what the slot already holds.
+    for (int w = 1; w < kW; ++w) m = umax(m, red[w]);
     const unsigned long long cur =
         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (m > cur) atomicMax(slot, m);
@@ -109,42 +121,16 @@ __device__ __forceinline__ TileCoord tile_coord(int nx, int ny) {
   return c;
 }
 
+// r = (T (x) I) rbar at one site, component of stage j.
+__device__ __forceinline__ double2 t_apply(int j, const double2 (&r)[3]) {
+  return make_double2(MB4_T[j][0] * r[0].x + MB4_T[j][1] * r[1].x + MB4_T[j][2] * r[2].x,
+                      MB4_T[j][0] * r[0].y + MB4_T[j][1] * r[1].y + MB4_T[j][2] * r[2].y);
+}
+
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_reset_stats(Stats* stats, int upto) {
   for (int i = threadIdx.x; i <= upto; i += 64) stats->rmax[i] = 0ull;
   if (threadIdx.x == 0) stats->u0max = 0ull;
-}
-
-// ---------------------------------------------------------------------------
-// At U = e_3 (x) u_0 every stage value and every Gauss node equals u_0 (the
-// Lagrange basis sums to one), so int A_{c_m,z} f(U_z) dz = c_m f(u_0) and
-// Phi_m = -h c_m f(u_0); Phibar_i = -h TC_i f(u_0) with TC = T^-1 c.
-__global__ __launch_bounds__(kTile) void k_first_residual(Lattice L, Planes3 phib, Stats* stats) {
-  const TileCoord c = tile_coord(L.nx, L.ny);
-  unsigned long long m = 0ull;
-  if (c.inside) {
-    const int nx = L.nx, ny = L.ny;
-    const int site = c.y * nx + c.x;
-    const int xl = c.x == 0 ? nx - 1 : c.x - 1, xr = c.x == nx - 1 ? 0 : c.x + 1;
-    const int yd = c.y == 0 ? ny - 1 : c.y - 1, yu = c.y == ny - 1 ? 0 : c.y + 1;
-    const double2 u = L.u0[site];
-    const double2 a = L.u0[c.y * nx + xl], b = L.u0[c.y * nx + xr];
-    const double2 d = L.u0[yd * nx + c.x], e = L.u0[yu * nx + c.x];
-    const double sp = (a.x + b.x) + (d.x + e.x);
-    const double sq = (a.y + b.y) + (d.y + e.y);
-    const double vs = L.V[site] + L.shift;
-    const double gn = L.g * (u.x * u.x + u.y * u.y);
-    // f = S grad H = (A q + g n q, -(A p + g n p))
-    const double fp = -L.t * sq + (vs + gn) * u.y;
-    const double fq = L.t * sp - (vs + gn) * u.x;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double k = -L.h * MB4_TC[i];
-      phib.s[i][site] = make_double2(k * fp, k * fq);
-    }
-    m = umax(abs_bits(u.x), abs_bits(u.y));
-  }
-  block_max_to(m, &stats->u0max);
 }
 
 // ---------------------------------------------------------------------------
@@ -165,11 +151,10 @@ __device__ __forceinline__ void site_update(const Lattice& L, const CPlanes3& Ui
     for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double dp = MB4_T[j][0] * r[0].x + MB4_T[j][1] * r[1].x + MB4_T[j][2] * r[2].x;
-      const double dq = MB4_T[j][0] * r[0].y + MB4_T[j][1] * r[1].y + MB4_T[j][2] * r[2].y;
-      Un[j].x += dp;
-      Un[j].y += dq;
-      rm = umax(rm, umax(abs_bits(dp), abs_bits(dq)));
+      const double2 d = t_apply(j, r);
+      Un[j].x += d.x;
+      Un[j].y += d.y;
+      rm = umax(rm, umax(abs_bits(d.x), abs_bits(d.y)));
     }
   }
 #pragma unroll
@@ -181,17 +166,35 @@ __device__ __forceinline__ void site_update(const Lattice& L, const CPlanes3& Ui
   }
 }
 
+// Final update or residual pass of Newton iteration `fin.prev` (see top).
+// `chk` skips the pass once an earlier iteration converged; `rslot` (may be
+// NULL) receives ||(T (x) I) rbar||_inf, used by the kernel-level entry point.
 template <bool FROM_U0, bool HAS_RBAR>
 __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 Uin, Planes3 Uout,
                                                            CPlanes3 rb, Planes3 phib,
                                                            unsigned long long* rslot,
-                                                           ConvCheck chk) {
-  if (skip_iteration(chk)) return;
+                                                           ConvCheck chk, ConvCheck fin,
+                                                           double2* u0_out) {
+  if (converged_at(chk)) return;
   __shared__ double2 sw[3][kTY + 2][kTX + 2];
   const int nx = L.nx, ny = L.ny;
   const TileCoord c = tile_coord(nx, ny);
-  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
 
+  if (HAS_RBAR && converged_at(fin)) {
+    // u_1 = U_{c_3} of the converged iterate, written over u_0 site by site.
+    if (c.inside) {
+      const int site = c.y * nx + c.x;
+      double2 r[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
+      const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
+      const double2 d = t_apply(2, r);
+      u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
+    }
+    return;
+  }
+
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   // Own position (wrapped when the tile overhangs the lattice: such a
   // position may still be the periodic neighbour of an inside site).
   const int gx = c.inside ? c.x : wrap(c.x, nx);
@@ -276,59 +279,236 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
   } else {
     rm = 0ull;
   }
-  if (rslot != nullptr) block_max_to(rm, rslot);
+  if (rslot != nullptr) block_max_to<kTile>(rm, rslot);
 }
 
 // ---------------------------------------------------------------------------
-// (I - h lambda_i J) r_i = b_i with b_i = -Phibar_i.  Per site the 2x2 block
-// I - h lambda_i J_site, J_site = [[a, bb], [-cc, -a]] with a = 2 g p q,
-// bb = A_jj + g (p^2 + 3 q^2), cc = A_jj + g (3 p^2 + q^2) (Eqs. JL, JR), is
-// inverted exactly (its determinant is 1 + (h lambda)^2 (bb cc - a^2)); the
-// hopping part of J couples neighbours through h lambda_i t (sum r_q,
-// -sum r_p), which the sweep takes from the previous iterate.
-template <bool FIRST>
+// Per site, the 2x2 block I - h lambda_i J_site with J_site = [[a, bb],
+// [-cc, -a]], a = 2 g p q, bb = A_jj + g (p^2 + 3 q^2), cc = A_jj +
+// g (3 p^2 + q^2) (Eqs. JL, JR), is inverted exactly: its determinant is
+// 1 + (h lambda)^2 (bb cc - a^2).  The hopping part of J couples neighbours
+// through h lambda_i t (sum r_q, -sum r_p), taken from the previous iterate.
+struct SiteBlock {
+  double a, bb, cc;
+};
+
+__device__ __forceinline__ SiteBlock site_block(const Lattice& L, double2 u, double v) {
+  const double vs = v + L.shift;
+  const double pp = u.x * u.x, qq = u.y * u.y;
+  SiteBlock s;
+  s.a = 2.0 * L.g * u.x * u.y;
+  s.bb = vs + L.g * (pp + 3.0 * qq);
+  s.cc = vs + L.g * (3.0 * pp + qq);
+  return s;
+}
+
+// r = (I - hl J_site)^-1 b, given inv = 1 / det(I - hl J_site).
+__device__ __forceinline__ double2 block_solve(const SiteBlock& s, double hl, double inv, double bp,
+                                               double bq) {
+  return make_double2(inv * ((1.0 + hl * s.a) * bp + hl * s.bb * bq),
+                      inv * ((1.0 - hl * s.a) * bq - hl * s.cc * bp));
+}
+
+// f(u_0) = S grad H = (A q + g n q, -(A p + g n p)) at one site.
+__device__ __forceinline__ double2 f_at(const Lattice& L, int gx, int gy, double2 u, double v) {
+  const int nx = L.nx, ny = L.ny;
+  const int xl = gx == 0 ? nx - 1 : gx - 1, xr = gx == nx - 1 ? 0 : gx + 1;
+  const int yd = gy == 0 ? ny - 1 : gy - 1, yu = gy == ny - 1 ? 0 : gy + 1;
+  const double2 a = L.u0[gy * nx + xl], b = L.u0[gy * nx + xr];
+  const double2 d = L.u0[yd * nx + gx], e = L.u0[yu * nx + gx];
+  const double sp = (a.x + b.x) + (d.x + e.x);
+  const double sq = (a.y + b.y) + (d.y + e.y);
+  const double vs = v + L.shift;
+  const double gn = L.g * (u.x * u.x + u.y * u.y);
+  return make_double2(-L.t * sq + (vs + gn) * u.y, L.t * sp - (vs + gn) * u.x);
+}
+
+// All H + 1 block-Jacobi sweeps of one stage solve in one pass (temporal
+// blocking).  A 512-thread block owns an output tile and loads the right-hand
+// side, u_0 and V once on the tile plus an H-site halo; the first sweep (from
+// r = 0) is local, the next H exchange neighbours through LDS, the valid zone
+// shrinking by one ring per sweep, and only the tile's interior goes back to
+// HBM.  Each region position computes the iterate of its (wrapped) lattice
+// site from its own region neighbours, so lattices smaller than the region
+// give the same values as large ones.  The region is always 64 x 16 = 1024
+// positions, two per thread, so the tile shrinks as the halo grows.
+//
+// FIRST: Newton iteration 1.  The right-hand side -Phibar_i = h TC_i f(u_0)
+// is built in place (TC = T^-1 c); ||u_0||_inf goes to first->u0max; block 0
+// clears `next` (the statistics of the following step); with store_rhs the
+// tile's Phibar is also written out (for extra plain sweeps).
+constexpr int kRX = 64;
+constexpr int kRY = 16;
+constexpr int kSolveThreads = 512;
+__host__ __device__ constexpr int solve_tile_x(int h) { return kRX - 2 * h; }
+__host__ __device__ constexpr int solve_tile_y(int h) { return kRY - 2 * h; }
+
+struct FirstArgs {
+  Stats* first;      // u0max target
+  Stats* next;       // cleared for the next step (may be NULL)
+  int next_upto;     // rmax[0..next_upto] cleared
+  bool store_rhs;    // also write Phibar of the tile
+};
+
+template <int H, bool FIRST>
+__global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
+                                                                 Planes3 phib_out, Planes3 rout,
+                                                                 unsigned long long* rslot,
+                                                                 ConvCheck chk, FirstArgs fa) {
+  if (converged_at(chk)) return;
+  constexpr int RX = kRX, RY = kRY, RN = RX * RY;
+  constexpr int TSX = solve_tile_x(H), TSY = solve_tile_y(H);
+  constexpr int PER = RN / kSolveThreads;
+  static_assert(RN % kSolveThreads == 0, "region must be a whole number of passes");
+  __shared__ double2 sr[3][RN];
+  const int nx = L.nx, ny = L.ny;
+  const int tiles_x = (nx + TSX - 1) / TSX;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int tx0 = (b % tiles_x) * TSX, ty0 = (b / tiles_x) * TSY;
+
+  if (FIRST && fa.next != nullptr && blockIdx.x == 0) {
+    for (int i = threadIdx.x; i <= fa.next_upto; i += kSolveThreads) fa.next->rmax[i] = 0ull;
+    if (threadIdx.x == 0) fa.next->u0max = 0ull;
+  }
+
+  double2 rhs[PER][3];
+  SiteBlock blk[PER];
+  double inv[PER][3];
+  int gsite[PER];
+  unsigned long long um = 0ull;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kSolveThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    const int gx = wrap(tx0 - H + lx, nx), gy = wrap(ty0 - H + ly, ny);
+    const int site = gy * nx + gx;
+    gsite[j] = site;
+    const double2 u = L.u0[site];
+    const double v = L.V[site];
+    blk[j] = site_block(L, u, v);
+    double2 f = make_double2(0.0, 0.0);
+    if (FIRST) {
+      f = f_at(L, gx, gy, u, v);
+      const bool out = lx >= H && lx < H + TSX && ly >= H && ly < H + TSY &&
+                       tx0 + lx - H < nx && ty0 + ly - H < ny;
+      if (out) um = umax(um, umax(abs_bits(u.x), abs_bits(u.y)));
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double hl = L.h * MB4_LAMBDA[i];
+      if (FIRST) {
+        const double k = L.h * MB4_TC[i];
+        rhs[j][i] = make_double2(k * f.x, k * f.y);
+      } else {
+        const double2 ph = phib_in.s[i][site];
+        rhs[j][i] = make_double2(-ph.x, -ph.y);
+      }
+      inv[j][i] = 1.0 / (1.0 + hl * hl * (blk[j].bb * blk[j].cc - blk[j].a * blk[j].a));
+      sr[i][idx] = block_solve(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
+    }
+  }
+  // Sweeps 2 .. H+1, one stage at a time so that only one stage's new values
+  // are live in registers: compute stage i from LDS, barrier, store it, and
+  // go on with stage i+1 (whose buffer nobody writes meanwhile).  The barrier
+  // before each compute orders it after the previous store of that buffer.
+#pragma unroll
+  for (int s = 0; s < H; ++s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double hl = L.h * MB4_LAMBDA[i];
+      const double ht = hl * L.t;
+      __syncthreads();
+      double2 rn[PER];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = threadIdx.x + j * kSolveThreads;
+        const int lx = idx % RX, ly = idx / RX;
+        if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
+          const double2 r1 = sr[i][idx - 1], r2 = sr[i][idx + 1];
+          const double2 r3 = sr[i][idx - RX], r4 = sr[i][idx + RX];
+          const double sp = (r1.x + r2.x) + (r3.x + r4.x);
+          const double sq = (r1.y + r2.y) + (r3.y + r4.y);
+          rn[j] = block_solve(blk[j], hl, inv[j][i], rhs[j][i].x - ht * sq,
+                              rhs[j][i].y + ht * sp);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = threadIdx.x + j * kSolveThreads;
+        const int lx = idx % RX, ly = idx / RX;
+        if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) sr[i][idx] = rn[j];
+      }
+    }
+  }
+  __syncthreads();
+  // Interior (valid after all sweeps) back to HBM; positions of the tile that
+  // overhang the lattice are not written.
+  unsigned long long rm = 0ull;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kSolveThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx >= H && lx < H + TSX && ly >= H && ly < H + TSY && tx0 + lx - H < nx &&
+        ty0 + ly - H < ny) {
+      double2 r[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        r[i] = sr[i][idx];
+        rout.s[i][gsite[j]] = r[i];
+        if (FIRST && fa.store_rhs)
+          phib_out.s[i][gsite[j]] = make_double2(-rhs[j][i].x, -rhs[j][i].y);
+      }
+      if (rslot != nullptr) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double2 d = t_apply(m, r);
+          rm = umax(rm, umax(abs_bits(d.x), abs_bits(d.y)));
+        }
+      }
+    }
+  }
+  if (rslot != nullptr) block_max_to<kSolveThreads>(rm, rslot);
+  if (FIRST) block_max_to<kSolveThreads>(um, &fa.first->u0max);
+}
+
+// One more block-Jacobi sweep from the iterate rin (solves with more than
+// four sweeps); rslot (may be NULL) receives ||(T (x) I) rout||_inf.
 __global__ __launch_bounds__(kTile) void k_stage_sweep(Lattice L, CPlanes3 phib, CPlanes3 rin,
-                                                       Planes3 rout, ConvCheck chk) {
-  if (skip_iteration(chk)) return;
+                                                       Planes3 rout, unsigned long long* rslot,
+                                                       ConvCheck chk) {
+  if (converged_at(chk)) return;
   const int nx = L.nx, ny = L.ny;
   const TileCoord c = tile_coord(nx, ny);
-  if (!c.inside) return;
-  const int site = c.y * nx + c.x;
-  const double2 u = L.u0[site];
-  const double vs = L.V[site] + L.shift;
-  const double g = L.g;
-  const double pp = u.x * u.x, qq = u.y * u.y;
-  const double a = 2.0 * g * u.x * u.y;
-  const double bb = vs + g * (pp + 3.0 * qq);
-  const double cc = vs + g * (3.0 * pp + qq);
-  const double bc_a2 = bb * cc - a * a;
-  int sl = 0, sr = 0, sd = 0, su = 0;
-  if (!FIRST) {
+  unsigned long long rm = 0ull;
+  if (c.inside) {
+    const int site = c.y * nx + c.x;
+    const SiteBlock blk = site_block(L, L.u0[site], L.V[site]);
     const int xl = c.x == 0 ? nx - 1 : c.x - 1, xr = c.x == nx - 1 ? 0 : c.x + 1;
     const int yd = c.y == 0 ? ny - 1 : c.y - 1, yu = c.y == ny - 1 ? 0 : c.y + 1;
-    sl = c.y * nx + xl;
-    sr = c.y * nx + xr;
-    sd = yd * nx + c.x;
-    su = yu * nx + c.x;
-  }
+    const int sl = c.y * nx + xl, sr = c.y * nx + xr, sd = yd * nx + c.x, su = yu * nx + c.x;
+    double2 r[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double hl = L.h * MB4_LAMBDA[i];
-    const double2 ph = phib.s[i][site];
-    double bp = -ph.x, bq = -ph.y;
-    if (!FIRST) {
+    for (int i = 0; i < 3; ++i) {
+      const double hl = L.h * MB4_LAMBDA[i];
+      const double2 ph = phib.s[i][site];
       const double2 r1 = rin.s[i][sl], r2 = rin.s[i][sr], r3 = rin.s[i][sd], r4 = rin.s[i][su];
       const double sp = (r1.x + r2.x) + (r3.x + r4.x);
       const double sq = (r1.y + r2.y) + (r3.y + r4.y);
       const double ht = hl * L.t;
-      bp -= ht * sq;
-      bq += ht * sp;
+      const double inv = 1.0 / (1.0 + hl * hl * (blk.bb * blk.cc - blk.a * blk.a));
+      r[i] = block_solve(blk, hl, inv, -ph.x - ht * sq, -ph.y + ht * sp);
+      rout.s[i][site] = r[i];
     }
-    const double inv = 1.0 / (1.0 + hl * hl * bc_a2);
-    const double rp = inv * ((1.0 + hl * a) * bp + hl * bb * bq);
-    const double rq = inv * ((1.0 - hl * a) * bq - hl * cc * bp);
-    rout.s[i][site] = make_double2(rp, rq);
+    if (rslot != nullptr) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double2 d = t_apply(m, r);
+        rm = umax(rm, umax(abs_bits(d.x), abs_bits(d.y)));
+      }
+    }
   }
+  if (rslot != nullptr) block_max_to<kTile>(rm, rslot);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,6 +619,11 @@ int tile_blocks(int nx, int ny) {
   return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
 }
 
+int solve_blocks(int nx, int ny, int h) {
+  const int tx = solve_tile_x(h), ty = solve_tile_y(h);
+  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -456,38 +641,80 @@ hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream) {
   MB4_LAUNCH(k_reset_stats, dim3(1), dim3(64), LaunchEvents{}, stats, upto);
 }
 
-hipError_t launch_first_residual(const Lattice& lat, Planes3 phib, Stats* stats,
-                                 hipStream_t stream, LaunchEvents ev) {
-  MB4_LAUNCH(k_first_residual, dim3(tile_blocks(lat.nx, lat.ny)), dim3(kTile), ev, lat, phib,
-             stats);
-}
-
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                                   bool has_rbar, bool from_u0, Planes3 phib,
-                                  unsigned long long* rslot, ConvCheck check, hipStream_t stream,
-                                  LaunchEvents ev) {
+                                  unsigned long long* rslot, ConvCheck check, ConvCheck fin,
+                                  double2* u0_out, hipStream_t stream, LaunchEvents ev) {
   const dim3 grid(tile_blocks(lat.nx, lat.ny)), block(kTile);
   if (from_u0 && has_rbar)
     MB4_LAUNCH((k_update_residual<true, true>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check);
+               rslot, check, fin, u0_out);
   else if (from_u0)
     MB4_LAUNCH((k_update_residual<true, false>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check);
+               rslot, check, fin, u0_out);
   else if (has_rbar)
     MB4_LAUNCH((k_update_residual<false, true>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check);
+               rslot, check, fin, u0_out);
   else
     MB4_LAUNCH((k_update_residual<false, false>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check);
+               rslot, check, fin, u0_out);
+}
+
+hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, int sweeps,
+                              unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                              LaunchEvents ev) {
+  const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
+  const Planes3 none{{nullptr, nullptr, nullptr}};
+  const FirstArgs fa{nullptr, nullptr, 0, false};
+  switch (sweeps) {
+    case 1:
+      MB4_LAUNCH((k_stage_solve<0, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
+                 fa);
+    case 2:
+      MB4_LAUNCH((k_stage_solve<1, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
+                 fa);
+    case 3:
+      MB4_LAUNCH((k_stage_solve<2, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
+                 fa);
+    case 4:
+      MB4_LAUNCH((k_stage_solve<3, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
+                 fa);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
+                              unsigned long long* rslot, Stats* first, Stats* next,
+                              int next_upto, Planes3 phib_out, hipStream_t stream,
+                              LaunchEvents ev) {
+  const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
+  const CPlanes3 none{{nullptr, nullptr, nullptr}};
+  const FirstArgs fa{first, next, next_upto, phib_out.s[0] != nullptr};
+  const ConvCheck nochk{nullptr, 0, 0.0};
+  switch (sweeps) {
+    case 1:
+      MB4_LAUNCH((k_stage_solve<0, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
+                 nochk, fa);
+    case 2:
+      MB4_LAUNCH((k_stage_solve<1, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
+                 nochk, fa);
+    case 3:
+      MB4_LAUNCH((k_stage_solve<2, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
+                 nochk, fa);
+    case 4:
+      MB4_LAUNCH((k_stage_solve<3, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
+                 nochk, fa);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
-                              bool first, ConvCheck check, hipStream_t stream, LaunchEvents ev) {
-  const dim3 grid(tile_blocks(lat.nx, lat.ny)), block(kTile);
-  if (first)
-    MB4_LAUNCH(k_stage_sweep<true>, grid, block, ev, lat, phib, rin, rout, check);
-  else
-    MB4_LAUNCH(k_stage_sweep<false>, grid, block, ev, lat, phib, rin, rout, check);
+                              unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                              LaunchEvents ev) {
+  MB4_LAUNCH(k_stage_sweep, dim3(tile_blocks(lat.nx, lat.ny)), dim3(kTile), ev, lat, phib, rin,
+             rout, rslot, check);
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -2,15 +2,17 @@
 //
 // A state owns the device fields of one lattice problem and drives
 // Algorithm 1 of Sakai et al. (arXiv 2003.04345) on one stream:
-//   per step: first transformed residual from u_0 (U^0 = e_3 (x) u_0), then
-//   Newton iterations l = 1, 2, ..., each = stage solve (k block-Jacobi
-//   sweeps, the three stages in one launch) + fused update/residual pass
-//   recording ||r^l||_inf.  Iterations are enqueued in batches sized by the
-//   previous step's count; every kernel of iteration l >= 2 returns at once
-//   when ||r^{l-1}||_inf already met the tolerance, so an over-long batch
-//   costs only empty launches.  One 8-byte-per-iteration read-back per batch
-//   decides acceptance on the host: u_1 = U_{c_3} becomes u_0 by a pointer
-//   swap (Sec. 2.2, last paragraph: c_3 = 1).
+//   per step, Newton iterations l = 1, 2, ..., each = stage solve (k
+//   block-Jacobi sweeps, the three stages in one launch, which also records
+//   ||r^l||_inf; in iteration 1 it builds the residual at U^0 = e_3 (x) u_0
+//   itself) + update pass.  The update pass of the iteration whose norm meets
+//   the tolerance writes u_1 = U_{c_3} over u_0 (Sec. 2.2, last paragraph:
+//   c_3 = 1); the others apply the Newton update and form the next residual.
+//   Iterations are enqueued in batches sized by the previous step's count;
+//   every kernel of iteration l >= 2 returns at once when ||r^{l-1}||_inf
+//   already met the tolerance, so an over-long batch costs only empty
+//   launches.  One 8-byte-per-iteration read-back per batch tells the host
+//   where the step converged.
 #include <float.h>
 #include <math.h>
 #include <stdarg.h>
@@ -34,7 +36,7 @@ namespace {
 
 constexpr double kDefaultEps = 1e-13;  // Sec. 3: epsilon = 1e-13
 constexpr int kDefaultMaxNewton = 50;
-constexpr int kDefaultSweeps = 4;
+constexpr int kDefaultSweeps = 3;
 constexpr int kMaxSweeps = 64;
 constexpr int64_t kMaxSites = int64_t(1) << 28;
 constexpr int kInitialPrediction = 3;
@@ -92,7 +94,13 @@ struct mb4_state {
   double2* phib[3] = {nullptr, nullptr, nullptr};
   double2* ra[3] = {nullptr, nullptr, nullptr};
   double2* rb[3] = {nullptr, nullptr, nullptr};
-  Stats* stats = nullptr;
+  // Newton statistics, double-buffered by attempt: attempt k uses
+  // stats[k & 1], which its first kernel found cleared, and clears
+  // stats[(k + 1) & 1] for the next one.  dbg_stats serves the kernel-level
+  // entry points.
+  Stats* stats[2] = {nullptr, nullptr};
+  Stats* dbg_stats = nullptr;
+  uint64_t attempt = 0;
   unsigned long long* h_stats = nullptr;  // pinned: u0max, rmax[0..kMaxNewton]
   double* partials = nullptr;
   double* eout = nullptr;
@@ -107,8 +115,8 @@ struct mb4_state {
     hipEvent_t a, b;
   };
   std::vector<Rec> prof_pending;
-  int64_t prof_launches[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_launches[6] = {0, 0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
   int64_t steps_done = 0;
   int last_iters = 0;
   int last_sweeps = 0;
@@ -121,7 +129,7 @@ namespace {
 // Device bytes of a state: V (8 B/site), u_0 (16), two stage-value fields
 // (2 x 48), the transformed residual (48), two stage-correction fields (2 x 48).
 size_t footprint_bytes(size_t sites, int nx, int ny) {
-  return sites * 264 + sizeof(Stats) + mb4::energy_partials_count(nx, ny) * sizeof(double) +
+  return sites * 264 + 3 * sizeof(Stats) + mb4::energy_partials_count(nx, ny) * sizeof(double) +
          8 * sizeof(double);
 }
 
@@ -186,10 +194,21 @@ int use_device(const mb4_state* s) {
   return MB4_OK;
 }
 
-enum KernelClass { kFirstResidual = 0, kSweepFirst = 1, kSweep = 2, kUpdateResidual = 3 };
-constexpr int kKernelClasses = 4;
-const char* const kKernelNames[kKernelClasses] = {"first_residual", "stage_sweep_first",
-                                                  "stage_sweep", "update_residual"};
+// Kernel classes for timing.  Update passes are recorded as kUpdateResidual
+// and classified when the step is decided: iteration 1 (which starts from
+// U = e_3 (x) u_0 and reads no U), later iterations, and the final update.
+enum KernelClass {
+  kFirstSolve = 0,
+  kStageSolve = 1,
+  kSweep = 2,
+  kUpdateResidualFirst = 3,
+  kUpdateResidual = 4,
+  kFinalUpdate = 5
+};
+constexpr int kKernelClasses = 6;
+const char* const kKernelNames[kKernelClasses] = {"stage_solve_first", "stage_solve",
+                                                  "stage_sweep", "update_residual_first",
+                                                  "update_residual", "final_update"};
 
 int prof_event(mb4_state* s, hipEvent_t* ev) {
   if (s->ev_used == s->ev_pool.size()) {
@@ -201,15 +220,23 @@ int prof_event(mb4_state* s, hipEvent_t* ev) {
   return MB4_OK;
 }
 
-// Adds the durations of the recorded launches of iterations <= last_iter
-// (iteration 0: the first residual) to the per-class totals.
-int prof_collect(mb4_state* s, int last_iter) {
+// Adds the durations of the recorded launches of iterations <= last_iter to
+// the per-class totals; the update pass of the converged iteration
+// `final_iter` (0: none) counts as the final update.
+int prof_collect(mb4_state* s, int last_iter, int final_iter) {
   for (const auto& r : s->prof_pending) {
     if (r.iter > last_iter) continue;
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
-    s->prof_launches[r.cls] += 1;
-    s->prof_ms[r.cls] += ms;
+    int cls = r.cls;
+    if (cls == kUpdateResidual) {
+      if (r.iter == final_iter)
+        cls = kFinalUpdate;
+      else if (r.iter == 1)
+        cls = kUpdateResidualFirst;
+    }
+    s->prof_launches[cls] += 1;
+    s->prof_ms[cls] += ms;
   }
   s->prof_pending.clear();
   s->ev_used = 0;
@@ -237,46 +264,66 @@ int launch_events(mb4_state* s, int cls, int iter, mb4::LaunchEvents* ev) {
     HIP_TRY(expr);                                        \
   } while (0)
 
-// Enqueues the stage solve of one Newton iteration: `sweeps` block-Jacobi
-// sweeps from r = 0 alternating between ra and rb; returns the planes that
-// hold the result.
-int enqueue_solve(mb4_state* s, const Lattice& L, CPlanes3 phib, ConvCheck chk, int iter,
+// Enqueues the stage solve of Newton iteration `iter`: up to four
+// block-Jacobi sweeps from r = 0 in one temporally blocked pass into ra (in
+// iteration 1 with the residual at U^0 built in place), then any further
+// sweeps one pass each, alternating between rb and ra.  The pass that
+// produces the solution records ||r^iter||_inf in st->rmax[iter].  `*result`
+// receives the planes that hold the solution.
+int enqueue_solve(mb4_state* s, const Lattice& L, int iter, Stats* st, Stats* next,
                   double2* const** result) {
-  for (int k = 0; k < s->sweeps; ++k) {
-    double2* const(&out)[3] = (k % 2 == 0) ? s->ra : s->rb;
-    double2* const(&in)[3] = (k % 2 == 0) ? s->rb : s->ra;
-    LAUNCH(s, k == 0 ? kSweepFirst : kSweep, iter,
-           mb4::launch_stage_sweep(L, phib, C(in), P(out), k == 0, chk, s->stream, ev_));
+  const ConvCheck chk = iter >= 2 ? ConvCheck{st, iter - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+  const int fused = std::min(s->sweeps, mb4::kMaxFusedSweeps);
+  const bool extra = s->sweeps > fused;
+  unsigned long long* rslot = &st->rmax[iter];
+  if (iter == 1) {
+    const Planes3 store = extra ? P(s->phib) : Planes3{{nullptr, nullptr, nullptr}};
+    LAUNCH(s, kFirstSolve, iter,
+           mb4::launch_first_solve(L, P(s->ra), fused, extra ? nullptr : rslot, st, next,
+                                   s->max_newton, store, s->stream, ev_));
+  } else {
+    LAUNCH(s, kStageSolve, iter,
+           mb4::launch_stage_solve(L, C(s->phib), P(s->ra), fused, extra ? nullptr : rslot, chk,
+                                   s->stream, ev_));
   }
-  *result = ((s->sweeps - 1) % 2 == 0) ? s->ra : s->rb;
+  double2* const* cur = s->ra;
+  for (int k = fused; k < s->sweeps; ++k) {
+    double2* const(&out)[3] = (cur == s->ra) ? s->rb : s->ra;
+    const CPlanes3 in{{cur[0], cur[1], cur[2]}};
+    LAUNCH(s, kSweep, iter,
+           mb4::launch_stage_sweep(L, C(s->phib), in, P(out),
+                                   k == s->sweeps - 1 ? rslot : nullptr, chk, s->stream, ev_));
+    cur = out;
+  }
+  *result = cur;
   return MB4_OK;
 }
 
 // One MB4 step (Algorithm 1, body of the time loop).
 int step_once(mb4_state* s) {
   const Lattice L = lattice_of(s);
-  HIP_TRY(mb4::launch_reset_stats(s->stats, s->max_newton, s->stream));
-  LAUNCH(s, kFirstResidual, 0,
-         mb4::launch_first_residual(L, P(s->phib), s->stats, s->stream, ev_));
+  Stats* st = s->stats[s->attempt & 1];
+  Stats* next = s->stats[(s->attempt + 1) & 1];
+  ++s->attempt;
   int done = 0;
   int batch = std::max(1, std::min(s->predicted, s->max_newton));
   for (;;) {
     const int upto = std::min(done + batch, s->max_newton);
     for (int l = done + 1; l <= upto; ++l) {
-      const ConvCheck chk = (l >= 2) ? ConvCheck{s->stats, l - 1, s->eps}
-                                     : ConvCheck{nullptr, 0, 0.0};
       double2* const* rfin = nullptr;
-      int rc = enqueue_solve(s, L, C(s->phib), chk, l, &rfin);
+      int rc = enqueue_solve(s, L, l, st, next, &rfin);
       if (rc != MB4_OK) return rc;
+      const ConvCheck chk = (l >= 2) ? ConvCheck{st, l - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+      const ConvCheck fin{st, l, s->eps};
       // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
       double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
       double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
       const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
       LAUNCH(s, kUpdateResidual, l,
              mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
-                                         &s->stats->rmax[l], chk, s->stream, ev_));
+                                         nullptr, chk, fin, s->u0, s->stream, ev_));
     }
-    HIP_TRY(hipMemcpyAsync(s->h_stats, s->stats, sizeof(unsigned long long) * (upto + 2),
+    HIP_TRY(hipMemcpyAsync(s->h_stats, st, sizeof(unsigned long long) * (upto + 2),
                            hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     const double u0max = bits_to_double(s->h_stats[0]);
@@ -284,27 +331,33 @@ int step_once(mb4_state* s) {
     for (int l = done + 1; l <= upto; ++l) {
       const double r = bits_to_double(s->h_stats[1 + l]);
       if (r <= tol) {
-        double2** uout = (l % 2 == 1) ? s->Ua : s->Ub;
-        std::swap(s->u0, uout[2]);  // u_1 = U_{c_3}
+        // The update pass of iteration l wrote u_1 = U_{c_3} over u_0.
         s->last_iters = l;
         s->last_sweeps = l * s->sweeps;
         s->last_rnorm = r;
         s->predicted = l;
-        return prof_collect(s, l);
+        return prof_collect(s, l, l);
       }
       if (!isfinite(r)) {
-        (void)prof_collect(s, upto);
+        (void)prof_collect(s, upto, 0);
         return fail(MB4_ENOCONV, "non-finite Newton update at iteration %d", l);
       }
     }
     if (upto >= s->max_newton) {
-      (void)prof_collect(s, upto);
+      (void)prof_collect(s, upto, 0);
       return fail(MB4_ENOCONV, "no convergence in %d Newton iterations (||r||_inf = %.3e, tol %.3e)",
                   s->max_newton, bits_to_double(s->h_stats[1 + upto]), tol);
     }
     done = upto;
     batch = 1;
   }
+}
+
+// Clears both step statistics blocks (after the state changes under them).
+int clear_stats(mb4_state* s) {
+  for (int k = 0; k < 2; ++k) HIP_TRY(hipMemsetAsync(s->stats[k], 0, sizeof(Stats), s->stream));
+  s->attempt = 0;
+  return MB4_OK;
 }
 
 int check_state(const mb4_state* s) {
@@ -393,19 +446,23 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     alloc_field(&s->ra[i]);
     alloc_field(&s->rb[i]);
   }
-  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->stats), sizeof(Stats));
+  for (int k = 0; k < 2; ++k)
+    if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->stats[k]), sizeof(Stats));
+  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->dbg_stats), sizeof(Stats));
   if (rc == MB4_OK)
     rc = dalloc(s, reinterpret_cast<void**>(&s->partials),
                 mb4::energy_partials_count(s->nx, s->ny) * sizeof(double));
   if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->eout), 8 * sizeof(double));
   if (rc == MB4_OK)
-    rc = halloc(s, reinterpret_cast<void**>(&s->h_stats), sizeof(Stats));
+    rc = halloc(s, reinterpret_cast<void**>(&s->h_stats), 2 * sizeof(Stats));
   if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_eout), 8 * sizeof(double));
   if (rc == MB4_OK) {
     e = hipMemcpyAsync(s->V, potential, s->sites * sizeof(double), hipMemcpyHostToDevice,
                        s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->u0, 0, field, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->stats, 0, sizeof(Stats), s->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+      e = hipMemsetAsync(s->stats[k], 0, sizeof(Stats), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->dbg_stats, 0, sizeof(Stats), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) rc = fail(MB4_EDEVICE, "initial upload: %s", hipGetErrorString(e));
   }
@@ -440,6 +497,7 @@ int mb4_set_state(mb4_state* s, const double* p, const double* q) {
   }
   HIP_TRY(hipMemcpyAsync(s->u0, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice,
                          s->stream));
+  if ((rc = clear_stats(s)) != MB4_OK) return rc;
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->steps_done = 0;
   s->predicted = kInitialPrediction;
@@ -468,6 +526,7 @@ int mb4_set_state_device(mb4_state* s, const double* d_p, const double* d_q) {
   if (d_p == nullptr || d_q == nullptr) return fail(MB4_EINVAL, "d_p and d_q must not be NULL");
   if ((rc = use_device(s)) != MB4_OK) return rc;
   HIP_TRY(mb4::launch_interleave(d_p, d_q, s->u0, int(s->sites), s->stream));
+  if ((rc = clear_stats(s)) != MB4_OK) return rc;
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->steps_done = 0;
   s->predicted = kInitialPrediction;
@@ -586,10 +645,11 @@ int mb4_newton_update(mb4_state* s, double* d_U, const double* d_rbar, double* d
   const bool has_r = d_rbar != nullptr;
   const CPlanes3 uin = cplanes_of(d_U, s->sites);
   const CPlanes3 rin = has_r ? cplanes_of(d_rbar, s->sites) : CPlanes3{{nullptr, nullptr, nullptr}};
-  HIP_TRY(mb4::launch_reset_stats(s->stats, 0, s->stream));
+  const ConvCheck none{nullptr, 0, 0.0};
+  HIP_TRY(mb4::launch_reset_stats(s->dbg_stats, 0, s->stream));
   HIP_TRY(mb4::launch_update_residual(lattice_of(s), uin, P(s->Ua), rin, has_r, false,
-                                      planes_of(d_phibar, s->sites), &s->stats->rmax[0],
-                                      ConvCheck{nullptr, 0, 0.0}, s->stream));
+                                      planes_of(d_phibar, s->sites), &s->dbg_stats->rmax[0], none,
+                                      none, nullptr, s->stream));
   if (has_r) {
     // The pass cannot update U in place (other blocks read its halo), so the
     // result goes through the state's stage buffer.
@@ -598,10 +658,11 @@ int mb4_newton_update(mb4_state* s, double* d_U, const double* d_rbar, double* d
       HIP_TRY(hipMemcpyAsync(uout.s[i], s->Ua[i], s->sites * sizeof(double2),
                              hipMemcpyDeviceToDevice, s->stream));
   }
-  HIP_TRY(hipMemcpyAsync(s->h_stats, s->stats, 2 * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, s->stream));
+  unsigned long long* h = s->h_stats + 2 + mb4::kMaxNewton;  // past the step statistics
+  HIP_TRY(hipMemcpyAsync(h, s->dbg_stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (rnorm) *rnorm = bits_to_double(s->h_stats[1]);
+  if (rnorm) *rnorm = bits_to_double(h[1]);
   return MB4_OK;
 }
 
@@ -616,12 +677,17 @@ int mb4_stage_solve(mb4_state* s, const double* d_phibar, double* d_rbar, int32_
   const Lattice L = lattice_of(s);
   const CPlanes3 ph = cplanes_of(d_phibar, s->sites);
   const Planes3 ext = planes_of(d_rbar, s->sites);
-  Planes3 prev{{nullptr, nullptr, nullptr}};
-  for (int k = 0; k < sweeps; ++k) {
-    const Planes3 out = (k == sweeps - 1) ? ext : ((k % 2 == 0) ? P(s->ra) : P(s->rb));
+  const ConvCheck none{nullptr, 0, 0.0};
+  const int fused = std::min(int(sweeps), mb4::kMaxFusedSweeps);
+  // Same kernels as a Newton iteration; the last pass writes the caller's
+  // planes.
+  Planes3 prev = (fused == sweeps) ? ext : P(s->ra);
+  HIP_TRY(mb4::launch_stage_solve(L, ph, prev, fused, nullptr, none, s->stream));
+  for (int k = fused; k < sweeps; ++k) {
+    const Planes3 out =
+        (k == sweeps - 1) ? ext : ((prev.s[0] == s->ra[0]) ? P(s->rb) : P(s->ra));
     const CPlanes3 in{{prev.s[0], prev.s[1], prev.s[2]}};
-    HIP_TRY(mb4::launch_stage_sweep(L, ph, in, out, k == 0, ConvCheck{nullptr, 0, 0.0},
-                                    s->stream));
+    HIP_TRY(mb4::launch_stage_sweep(L, ph, in, out, nullptr, none, s->stream));
     prev = out;
   }
   HIP_TRY(hipStreamSynchronize(s->stream));

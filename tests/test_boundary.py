@@ -150,7 +150,7 @@ def test_null_arguments(lib):
 
 def test_options_default_values(lib):
     o = M.mb4_options_default()
-    assert o.eps == 1e-13 and o.max_newton == 50 and o.inner_sweeps == 4
+    assert o.eps == 1e-13 and o.max_newton == 50 and o.inner_sweeps == 3
     assert o.stream is None and o.mem_budget == 0
 
 
