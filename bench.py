@@ -109,6 +109,21 @@ def cpu_baseline(sample_side: int, sample_steps: int, workload: str) -> dict:
                        f"{dt:.1f} s")}
 
 
+def copy_calibration(mib: int) -> int:
+    """Five plain device-to-device copies of `mib` MiB: each moves exactly
+    mib MiB in and mib MiB out of HBM, which calibrates the FETCH_SIZE and
+    WRITE_SIZE counters against known bytes."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "copies": 5}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +137,12 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel events (no roofline entry)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (reference for HBM "
+                         "byte counters) and exit")
     args = ap.parse_args(argv)
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
