@@ -7,17 +7,14 @@
 
 namespace mb4 {
 
-// Largest Newton iteration count a state may request; the stats block keeps
-// one ||r||_inf slot per iteration.
+// Largest Newton iteration count a state may request.
 constexpr int kMaxNewton = 1000;
 
-// Device-side step statistics.  Non-negative doubles are stored as their
-// IEEE bit patterns so that an unsigned 64-bit atomicMax is an exact,
-// order-independent maximum.
-struct Stats {
-  unsigned long long u0max;                 // ||u_0||_inf of the current step
-  unsigned long long rmax[kMaxNewton + 1];  // rmax[l] = ||r^l||_inf, l >= 1
-};
+// Statistics of one step live in a record of unsigned 64-bit words:
+// rec[0] = ||u_0||_inf, rec[l] = ||r^l||_inf for Newton iteration l >= 1.
+// Non-negative doubles are stored as their IEEE bit patterns, so that an
+// unsigned atomicMax is an exact, order-independent maximum (and a NaN, whose
+// patterns sort above +inf, survives it).
 
 // The lattice problem as the kernels see it: periodic nx x ny, hopping -t on
 // the four links, on-site A_jj = V_j + shift, nonlinearity g, time step h.
@@ -41,8 +38,8 @@ struct CPlanes3 {
 // return at once when iteration l-1 passed it; the update pass of iteration l
 // turns into the final update when iteration l passed it.
 struct ConvCheck {
-  const Stats* stats;  // NULL: the test is false
-  int prev;            // iteration whose norm decides
+  const unsigned long long* rec;  // step record; NULL: the test is false
+  int prev;                       // iteration whose norm decides
   double eps;
 };
 
@@ -53,18 +50,17 @@ struct LaunchEvents {
 };
 
 // Kernel launchers (each enqueues on `stream`; return hipSuccess or an error).
-hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream);
+// p[0 .. n) = 0 (a kernel, so that it may sit in a captured graph).
+hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 
 // Newton iteration 1, stage solve: `sweeps` (1..4) block-Jacobi sweeps of
 // (I - h lambda_i J) r_i = -Phibar_i with Phibar_i = -h TC_i f(u_0) (the
 // residual at U^0 = e_3 (x) u_0) built in place, into rout.  Records
-// ||u_0||_inf in first->u0max and ||(T (x) I) r||_inf in *rslot (if not
-// NULL), clears `next` (if not NULL) up to rmax[next_upto], and writes that
-// Phibar to phib_out when phib_out.s[0] is not NULL.
+// ||u_0||_inf in *u0max_slot and ||(T (x) I) r||_inf in *rslot (if not NULL),
+// and writes that Phibar to phib_out when phib_out.s[0] is not NULL.
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
-                              unsigned long long* rslot, Stats* first, Stats* next,
-                              int next_upto, Planes3 phib_out, hipStream_t stream,
-                              LaunchEvents ev = {});
+                              unsigned long long* rslot, unsigned long long* u0max_slot,
+                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {});
 
 // Newton iteration l >= 2 (or a kernel-level call), stage solve: `sweeps`
 // (1..4) block-Jacobi sweeps from r = 0 for the three stage systems

@@ -27,6 +27,8 @@
 #include <float.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "mb4_constants.h"
 #include "mb4_internal.h"
 
@@ -74,9 +76,9 @@ __device__ __forceinline__ double conv_tol(double eps, double u0max) {
 
 // True when Newton iteration c.prev (>= 1) already met the tolerance.
 __device__ __forceinline__ bool converged_at(const ConvCheck& c) {
-  if (c.stats == nullptr) return false;
-  const double u0max = bits_double(c.stats->u0max);
-  const double r = bits_double(c.stats->rmax[c.prev]);
+  if (c.rec == nullptr) return false;
+  const double u0max = bits_double(c.rec[0]);
+  const double r = bits_double(c.rec[c.prev]);
   return r <= conv_tol(c.eps, u0max);
 }
 
@@ -128,9 +130,8 @@ __device__ __forceinline__ double2 t_apply(int j, const double2 (&r)[3]) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_reset_stats(Stats* stats, int upto) {
-  for (int i = threadIdx.x; i <= upto; i += 64) stats->rmax[i] = 0ull;
-  if (threadIdx.x == 0) stats->u0max = 0ull;
+__global__ __launch_bounds__(256) void k_clear_u64(unsigned long long* p, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -334,9 +335,8 @@ __device__ __forceinline__ double2 f_at(const Lattice& L, int gx, int gy, double
 // positions, two per thread, so the tile shrinks as the halo grows.
 //
 // FIRST: Newton iteration 1.  The right-hand side -Phibar_i = h TC_i f(u_0)
-// is built in place (TC = T^-1 c); ||u_0||_inf goes to first->u0max; block 0
-// clears `next` (the statistics of the following step); with store_rhs the
-// tile's Phibar is also written out (for extra plain sweeps).
+// is built in place (TC = T^-1 c); ||u_0||_inf goes to *u0max_slot; with
+// store_rhs the tile's Phibar is also written out (for extra plain sweeps).
 constexpr int kRX = 64;
 constexpr int kRY = 16;
 constexpr int kSolveThreads = 512;
@@ -344,10 +344,8 @@ __host__ __device__ constexpr int solve_tile_x(int h) { return kRX - 2 * h; }
 __host__ __device__ constexpr int solve_tile_y(int h) { return kRY - 2 * h; }
 
 struct FirstArgs {
-  Stats* first;      // u0max target
-  Stats* next;       // cleared for the next step (may be NULL)
-  int next_upto;     // rmax[0..next_upto] cleared
-  bool store_rhs;    // also write Phibar of the tile
+  unsigned long long* u0max_slot;  // ||u_0||_inf target
+  bool store_rhs;                  // also write Phibar of the tile
 };
 
 template <int H, bool FIRST>
@@ -365,11 +363,6 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
   const int tiles_x = (nx + TSX - 1) / TSX;
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int tx0 = (b % tiles_x) * TSX, ty0 = (b / tiles_x) * TSY;
-
-  if (FIRST && fa.next != nullptr && blockIdx.x == 0) {
-    for (int i = threadIdx.x; i <= fa.next_upto; i += kSolveThreads) fa.next->rmax[i] = 0ull;
-    if (threadIdx.x == 0) fa.next->u0max = 0ull;
-  }
 
   double2 rhs[PER][3];
   SiteBlock blk[PER];
@@ -469,7 +462,7 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
     }
   }
   if (rslot != nullptr) block_max_to<kSolveThreads>(rm, rslot);
-  if (FIRST) block_max_to<kSolveThreads>(um, &fa.first->u0max);
+  if (FIRST) block_max_to<kSolveThreads>(um, fa.u0max_slot);
 }
 
 // One more block-Jacobi sweep from the iterate rin (solves with more than
@@ -637,8 +630,9 @@ int solve_blocks(int nx, int ny, int h) {
     return hipGetLastError();                                                                \
   } while (0)
 
-hipError_t launch_reset_stats(Stats* stats, int upto, hipStream_t stream) {
-  MB4_LAUNCH(k_reset_stats, dim3(1), dim3(64), LaunchEvents{}, stats, upto);
+hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream) {
+  const int blocks = std::max(1, std::min((n + 255) / 256, 64));
+  MB4_LAUNCH(k_clear_u64, dim3(blocks), dim3(256), LaunchEvents{}, p, n);
 }
 
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
@@ -665,7 +659,7 @@ hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, i
                               LaunchEvents ev) {
   const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
   const Planes3 none{{nullptr, nullptr, nullptr}};
-  const FirstArgs fa{nullptr, nullptr, 0, false};
+  const FirstArgs fa{nullptr, false};
   switch (sweeps) {
     case 1:
       MB4_LAUNCH((k_stage_solve<0, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
@@ -685,12 +679,11 @@ hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, i
 }
 
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
-                              unsigned long long* rslot, Stats* first, Stats* next,
-                              int next_upto, Planes3 phib_out, hipStream_t stream,
-                              LaunchEvents ev) {
+                              unsigned long long* rslot, unsigned long long* u0max_slot,
+                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev) {
   const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
   const CPlanes3 none{{nullptr, nullptr, nullptr}};
-  const FirstArgs fa{first, next, next_upto, phib_out.s[0] != nullptr};
+  const FirstArgs fa{u0max_slot, phib_out.s[0] != nullptr};
   const ConvCheck nochk{nullptr, 0, 0.0};
   switch (sweeps) {
     case 1:

@@ -8,11 +8,12 @@
 //   itself) + update pass.  The update pass of the iteration whose norm meets
 //   the tolerance writes u_1 = U_{c_3} over u_0 (Sec. 2.2, last paragraph:
 //   c_3 = 1); the others apply the Newton update and form the next residual.
-//   Iterations are enqueued in batches sized by the previous step's count;
-//   every kernel of iteration l >= 2 returns at once when ||r^{l-1}||_inf
-//   already met the tolerance, so an over-long batch costs only empty
-//   launches.  One 8-byte-per-iteration read-back per batch tells the host
-//   where the step converged.
+//   Every kernel of iteration l >= 2 returns at once when ||r^{l-1}||_inf
+//   already met the tolerance.  Since u_0 is updated in place and no buffer
+//   moves, up to kBatch steps are enqueued back to back with the previous
+//   step's iteration count, and one read-back of their statistics per batch
+//   tells the host where each converged (see run_batch for the rare step
+//   that needs more iterations).
 #include <float.h>
 #include <math.h>
 #include <stdarg.h>
@@ -30,7 +31,6 @@ using mb4::CPlanes3;
 using mb4::ConvCheck;
 using mb4::Lattice;
 using mb4::Planes3;
-using mb4::Stats;
 
 namespace {
 
@@ -40,6 +40,7 @@ constexpr int kDefaultSweeps = 3;
 constexpr int kMaxSweeps = 64;
 constexpr int64_t kMaxSites = int64_t(1) << 28;
 constexpr int kInitialPrediction = 3;
+constexpr int kBatch = 32;  // steps enqueued per host round trip
 
 thread_local std::string g_detail;
 
@@ -94,14 +95,16 @@ struct mb4_state {
   double2* phib[3] = {nullptr, nullptr, nullptr};
   double2* ra[3] = {nullptr, nullptr, nullptr};
   double2* rb[3] = {nullptr, nullptr, nullptr};
-  // Newton statistics, double-buffered by attempt: attempt k uses
-  // stats[k & 1], which its first kernel found cleared, and clears
-  // stats[(k + 1) & 1] for the next one.  dbg_stats serves the kernel-level
-  // entry points.
-  Stats* stats[2] = {nullptr, nullptr};
-  Stats* dbg_stats = nullptr;
-  uint64_t attempt = 0;
-  unsigned long long* h_stats = nullptr;  // pinned: u0max, rmax[0..kMaxNewton]
+  // Newton statistics: a ring of kBatch step records of rec_len words
+  // (rec[0] = ||u_0||_inf, rec[l] = ||r^l||_inf, l = 1 .. max_newton), one
+  // per step of a batch, cleared when the batch starts; h_ring is its pinned
+  // host copy.  dbg_rec serves the kernel-level entry points.
+  unsigned long long* ring = nullptr;
+  unsigned long long* h_ring = nullptr;
+  unsigned long long* dbg_rec = nullptr;
+  unsigned long long* h_dbg = nullptr;
+  int rec_len = 0;
+  std::vector<double> last_res;  // ||r^l||_inf of the last accepted step
   double* partials = nullptr;
   double* eout = nullptr;
   double* h_eout = nullptr;  // pinned, 6 doubles
@@ -111,7 +114,7 @@ struct mb4_state {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   struct Rec {
-    int cls, iter;
+    int cls, step, iter;
     hipEvent_t a, b;
   };
   std::vector<Rec> prof_pending;
@@ -127,10 +130,11 @@ struct mb4_state {
 namespace {
 
 // Device bytes of a state: V (8 B/site), u_0 (16), two stage-value fields
-// (2 x 48), the transformed residual (48), two stage-correction fields (2 x 48).
-size_t footprint_bytes(size_t sites, int nx, int ny) {
-  return sites * 264 + 3 * sizeof(Stats) + mb4::energy_partials_count(nx, ny) * sizeof(double) +
-         8 * sizeof(double);
+// (2 x 48), the transformed residual (48), two stage-correction fields
+// (2 x 48); plus the statistics records and the energy partial sums.
+size_t footprint_bytes(size_t sites, int nx, int ny, int max_newton) {
+  return sites * 264 + size_t(kBatch + 1) * size_t(max_newton + 1) * 8 +
+         mb4::energy_partials_count(nx, ny) * sizeof(double) + 8 * sizeof(double);
 }
 
 int dalloc(mb4_state* s, void** p, size_t bytes) {
@@ -220,17 +224,19 @@ int prof_event(mb4_state* s, hipEvent_t* ev) {
   return MB4_OK;
 }
 
-// Adds the durations of the recorded launches of iterations <= last_iter to
-// the per-class totals; the update pass of the converged iteration
-// `final_iter` (0: none) counts as the final update.
-int prof_collect(mb4_state* s, int last_iter, int final_iter) {
+// Adds the durations of the recorded launches to the per-class totals.
+// Step k of the batch converged at iteration m[k] (0: it did not); its
+// launches of later iterations returned at once and are not counted, and its
+// update pass of iteration m[k] counts as the final update.
+int prof_collect(mb4_state* s, const std::vector<int>& m) {
   for (const auto& r : s->prof_pending) {
-    if (r.iter > last_iter) continue;
+    const int mk = (r.step < int(m.size())) ? m[r.step] : 0;
+    if (mk > 0 && r.iter > mk) continue;
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
     int cls = r.cls;
     if (cls == kUpdateResidual) {
-      if (r.iter == final_iter)
+      if (r.iter == mk)
         cls = kFinalUpdate;
       else if (r.iter == 1)
         cls = kUpdateResidualFirst;
@@ -245,44 +251,44 @@ int prof_collect(mb4_state* s, int last_iter, int final_iter) {
 
 // Events for one launch: a fresh pair from the pool when profiling (the
 // launch records its own start/stop timestamps), none otherwise.
-int launch_events(mb4_state* s, int cls, int iter, mb4::LaunchEvents* ev) {
+int launch_events(mb4_state* s, int cls, int step, int iter, mb4::LaunchEvents* ev) {
   *ev = mb4::LaunchEvents{};
   if (!s->prof_on) return MB4_OK;
   int rc = prof_event(s, &ev->start);
   if (rc == MB4_OK) rc = prof_event(s, &ev->stop);
   if (rc != MB4_OK) return rc;
-  s->prof_pending.push_back(mb4_state::Rec{cls, iter, ev->start, ev->stop});
+  s->prof_pending.push_back(mb4_state::Rec{cls, step, iter, ev->start, ev->stop});
   return MB4_OK;
 }
 
 // Enqueues one kernel launch; `expr` may use the LaunchEvents `ev_`.
-#define LAUNCH(s, cls, iter, expr)                        \
-  do {                                                    \
-    mb4::LaunchEvents ev_;                                \
-    const int rc_ = launch_events((s), (cls), (iter), &ev_); \
-    if (rc_ != MB4_OK) return rc_;                        \
-    HIP_TRY(expr);                                        \
+#define LAUNCH(s, cls, step, iter, expr)                          \
+  do {                                                            \
+    mb4::LaunchEvents ev_;                                        \
+    const int rc_ = launch_events((s), (cls), (step), (iter), &ev_); \
+    if (rc_ != MB4_OK) return rc_;                                \
+    HIP_TRY(expr);                                                \
   } while (0)
 
-// Enqueues the stage solve of Newton iteration `iter`: up to four
-// block-Jacobi sweeps from r = 0 in one temporally blocked pass into ra (in
-// iteration 1 with the residual at U^0 built in place), then any further
-// sweeps one pass each, alternating between rb and ra.  The pass that
-// produces the solution records ||r^iter||_inf in st->rmax[iter].  `*result`
-// receives the planes that hold the solution.
-int enqueue_solve(mb4_state* s, const Lattice& L, int iter, Stats* st, Stats* next,
+// Enqueues the stage solve of Newton iteration `iter` of step `step` of the
+// batch (record `rec`): up to four block-Jacobi sweeps from r = 0 in one
+// temporally blocked pass into ra (in iteration 1 with the residual at U^0
+// built in place), then any further sweeps one pass each, alternating between
+// rb and ra.  The pass that produces the solution records ||r^iter||_inf in
+// rec[iter].  `*result` receives the planes that hold the solution.
+int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned long long* rec,
                   double2* const** result) {
-  const ConvCheck chk = iter >= 2 ? ConvCheck{st, iter - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+  const ConvCheck chk = iter >= 2 ? ConvCheck{rec, iter - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
   const int fused = std::min(s->sweeps, mb4::kMaxFusedSweeps);
   const bool extra = s->sweeps > fused;
-  unsigned long long* rslot = &st->rmax[iter];
+  unsigned long long* rslot = rec + iter;
   if (iter == 1) {
     const Planes3 store = extra ? P(s->phib) : Planes3{{nullptr, nullptr, nullptr}};
-    LAUNCH(s, kFirstSolve, iter,
-           mb4::launch_first_solve(L, P(s->ra), fused, extra ? nullptr : rslot, st, next,
-                                   s->max_newton, store, s->stream, ev_));
+    LAUNCH(s, kFirstSolve, step, iter,
+           mb4::launch_first_solve(L, P(s->ra), fused, extra ? nullptr : rslot, rec, store,
+                                   s->stream, ev_));
   } else {
-    LAUNCH(s, kStageSolve, iter,
+    LAUNCH(s, kStageSolve, step, iter,
            mb4::launch_stage_solve(L, C(s->phib), P(s->ra), fused, extra ? nullptr : rslot, chk,
                                    s->stream, ev_));
   }
@@ -290,7 +296,7 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int iter, Stats* st, Stats* ne
   for (int k = fused; k < s->sweeps; ++k) {
     double2* const(&out)[3] = (cur == s->ra) ? s->rb : s->ra;
     const CPlanes3 in{{cur[0], cur[1], cur[2]}};
-    LAUNCH(s, kSweep, iter,
+    LAUNCH(s, kSweep, step, iter,
            mb4::launch_stage_sweep(L, C(s->phib), in, P(out),
                                    k == s->sweeps - 1 ? rslot : nullptr, chk, s->stream, ev_));
     cur = out;
@@ -299,65 +305,116 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int iter, Stats* st, Stats* ne
   return MB4_OK;
 }
 
-// One MB4 step (Algorithm 1, body of the time loop).
-int step_once(mb4_state* s) {
-  const Lattice L = lattice_of(s);
-  Stats* st = s->stats[s->attempt & 1];
-  Stats* next = s->stats[(s->attempt + 1) & 1];
-  ++s->attempt;
-  int done = 0;
-  int batch = std::max(1, std::min(s->predicted, s->max_newton));
-  for (;;) {
-    const int upto = std::min(done + batch, s->max_newton);
-    for (int l = done + 1; l <= upto; ++l) {
-      double2* const* rfin = nullptr;
-      int rc = enqueue_solve(s, L, l, st, next, &rfin);
-      if (rc != MB4_OK) return rc;
-      const ConvCheck chk = (l >= 2) ? ConvCheck{st, l - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
-      const ConvCheck fin{st, l, s->eps};
-      // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
-      double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
-      double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
-      const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
-      LAUNCH(s, kUpdateResidual, l,
-             mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
-                                         nullptr, chk, fin, s->u0, s->stream, ev_));
-    }
-    HIP_TRY(hipMemcpyAsync(s->h_stats, st, sizeof(unsigned long long) * (upto + 2),
-                           hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    const double u0max = bits_to_double(s->h_stats[0]);
-    const double tol = conv_tol(s->eps, u0max);
-    for (int l = done + 1; l <= upto; ++l) {
-      const double r = bits_to_double(s->h_stats[1 + l]);
-      if (r <= tol) {
-        // The update pass of iteration l wrote u_1 = U_{c_3} over u_0.
-        s->last_iters = l;
-        s->last_sweeps = l * s->sweeps;
-        s->last_rnorm = r;
-        s->predicted = l;
-        return prof_collect(s, l, l);
-      }
-      if (!isfinite(r)) {
-        (void)prof_collect(s, upto, 0);
-        return fail(MB4_ENOCONV, "non-finite Newton update at iteration %d", l);
-      }
-    }
-    if (upto >= s->max_newton) {
-      (void)prof_collect(s, upto, 0);
-      return fail(MB4_ENOCONV, "no convergence in %d Newton iterations (||r||_inf = %.3e, tol %.3e)",
-                  s->max_newton, bits_to_double(s->h_stats[1 + upto]), tol);
-    }
-    done = upto;
-    batch = 1;
+// Enqueues Newton iterations first .. last of step `step` (record `rec`).
+// The update pass of the iteration whose norm meets the tolerance writes
+// u_1 = U_{c_3} over u_0; kernels of later iterations return at once.
+int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
+                       int first, int last) {
+  for (int l = first; l <= last; ++l) {
+    double2* const* rfin = nullptr;
+    const int rc = enqueue_solve(s, L, step, l, rec, &rfin);
+    if (rc != MB4_OK) return rc;
+    const ConvCheck chk = (l >= 2) ? ConvCheck{rec, l - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+    const ConvCheck fin{rec, l, s->eps};
+    // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
+    double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
+    double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
+    const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
+    LAUNCH(s, kUpdateResidual, step, l,
+           mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
+                                       nullptr, chk, fin, s->u0, s->stream, ev_));
   }
+  return MB4_OK;
 }
 
-// Clears both step statistics blocks (after the state changes under them).
-int clear_stats(mb4_state* s) {
-  for (int k = 0; k < 2; ++k) HIP_TRY(hipMemsetAsync(s->stats[k], 0, sizeof(Stats), s->stream));
-  s->attempt = 0;
-  return MB4_OK;
+// First iteration <= last whose norm in host record hrec met the tolerance;
+// 0 if none; -1 if a norm up to `last` is not finite.
+int converged_iteration(const mb4_state* s, const unsigned long long* hrec, int last) {
+  const double tol = conv_tol(s->eps, bits_to_double(hrec[0]));
+  for (int l = 1; l <= last; ++l) {
+    const double r = bits_to_double(hrec[l]);
+    if (r <= tol) return l;
+    if (!isfinite(r)) return -1;
+  }
+  return 0;
+}
+
+void accept(mb4_state* s, const unsigned long long* hrec, int m) {
+  s->last_iters = m;
+  s->last_sweeps = m * s->sweeps;
+  s->last_rnorm = bits_to_double(hrec[m]);
+  s->last_res.assign(size_t(m), 0.0);
+  for (int l = 1; l <= m; ++l) s->last_res[l - 1] = bits_to_double(hrec[l]);
+  s->predicted = m;
+  ++s->steps_done;
+}
+
+// Fast path: `count` <= kBatch steps enqueued back to back, each with
+// `iters` Newton iterations, and one read-back for all of them.  A step that
+// converged in time wrote u_1 over u_0, so the next step starts from it.  If
+// step k did not converge in time, u_0 kept its value, the later steps of the
+// batch repeated step k's computation exactly (every kernel is
+// deterministic) and changed nothing; *accepted = k tells the caller where to
+// continue.
+int run_batch(mb4_state* s, int count, int iters, int* accepted) {
+  const Lattice L = lattice_of(s);
+  const int words = count * s->rec_len;
+  HIP_TRY(mb4::launch_clear(s->ring, words, s->stream));
+  for (int k = 0; k < count; ++k) {
+    const int rc = enqueue_iterations(s, L, k, s->ring + size_t(k) * s->rec_len, 1, iters);
+    if (rc != MB4_OK) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(s->h_ring, s->ring, sizeof(unsigned long long) * words,
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  std::vector<int> m(size_t(count), 0);
+  int k = 0;
+  for (; k < count; ++k) {
+    const unsigned long long* hrec = s->h_ring + size_t(k) * s->rec_len;
+    const int mk = converged_iteration(s, hrec, iters);
+    if (mk <= 0) break;
+    m[k] = mk;
+    accept(s, hrec, mk);
+  }
+  *accepted = k;
+  return prof_collect(s, m);
+}
+
+// Slow path: one step with batches of iterations until it converges or
+// max_newton is reached (Sec. 2.2: failure is reported, h is not changed).
+int step_single(mb4_state* s) {
+  const Lattice L = lattice_of(s);
+  unsigned long long* rec = s->ring;
+  HIP_TRY(mb4::launch_clear(rec, s->rec_len, s->stream));
+  int done = 0;
+  int batch = std::max(1, std::min(s->predicted + 1, s->max_newton));
+  for (;;) {
+    const int upto = std::min(done + batch, s->max_newton);
+    int rc = enqueue_iterations(s, L, 0, rec, done + 1, upto);
+    if (rc != MB4_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(s->h_ring, rec, sizeof(unsigned long long) * (upto + 1),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const int m = converged_iteration(s, s->h_ring, upto);
+    if (m > 0) {
+      accept(s, s->h_ring, m);
+      return prof_collect(s, std::vector<int>{m});
+    }
+    if (m < 0) {
+      (void)prof_collect(s, std::vector<int>{0});
+      return fail(MB4_ENOCONV, "non-finite Newton update (step %lld)",
+                  static_cast<long long>(s->steps_done + 1));
+    }
+    if (upto >= s->max_newton) {
+      (void)prof_collect(s, std::vector<int>{0});
+      return fail(MB4_ENOCONV,
+                  "no convergence in %d Newton iterations (||r||_inf = %.3e, tol %.3e)",
+                  s->max_newton, bits_to_double(s->h_ring[upto]),
+                  conv_tol(s->eps, bits_to_double(s->h_ring[0])));
+    }
+    done = upto;
+    batch = 2;
+  }
 }
 
 int check_state(const mb4_state* s) {
@@ -411,7 +468,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   }
   if (!all_finite(potential, size_t(sites)))
     return fail(MB4_EINVAL, "potential has non-finite entries");
-  const size_t need = footprint_bytes(size_t(sites), lattice->nx, lattice->ny);
+  const size_t need = footprint_bytes(size_t(sites), lattice->nx, lattice->ny, o.max_newton);
   if (o.mem_budget != 0 && need > o.mem_budget)
     return fail(MB4_ENOMEM, "state needs %zu bytes, above mem_budget %llu", need,
                 static_cast<unsigned long long>(o.mem_budget));
@@ -446,23 +503,22 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     alloc_field(&s->ra[i]);
     alloc_field(&s->rb[i]);
   }
-  for (int k = 0; k < 2; ++k)
-    if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->stats[k]), sizeof(Stats));
-  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->dbg_stats), sizeof(Stats));
+  s->rec_len = s->max_newton + 1;
+  const size_t ring_bytes = size_t(kBatch) * s->rec_len * sizeof(unsigned long long);
+  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->ring), ring_bytes);
+  if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->dbg_rec), 2 * sizeof(unsigned long long));
   if (rc == MB4_OK)
     rc = dalloc(s, reinterpret_cast<void**>(&s->partials),
                 mb4::energy_partials_count(s->nx, s->ny) * sizeof(double));
   if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->eout), 8 * sizeof(double));
-  if (rc == MB4_OK)
-    rc = halloc(s, reinterpret_cast<void**>(&s->h_stats), 2 * sizeof(Stats));
+  if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_ring), ring_bytes);
+  if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_dbg), 2 * sizeof(unsigned long long));
   if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_eout), 8 * sizeof(double));
   if (rc == MB4_OK) {
     e = hipMemcpyAsync(s->V, potential, s->sites * sizeof(double), hipMemcpyHostToDevice,
                        s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->u0, 0, field, s->stream);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k)
-      e = hipMemsetAsync(s->stats[k], 0, sizeof(Stats), s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->dbg_stats, 0, sizeof(Stats), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ring, 0, ring_bytes, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) rc = fail(MB4_EDEVICE, "initial upload: %s", hipGetErrorString(e));
   }
@@ -497,7 +553,6 @@ int mb4_set_state(mb4_state* s, const double* p, const double* q) {
   }
   HIP_TRY(hipMemcpyAsync(s->u0, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice,
                          s->stream));
-  if ((rc = clear_stats(s)) != MB4_OK) return rc;
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->steps_done = 0;
   s->predicted = kInitialPrediction;
@@ -526,7 +581,6 @@ int mb4_set_state_device(mb4_state* s, const double* d_p, const double* d_q) {
   if (d_p == nullptr || d_q == nullptr) return fail(MB4_EINVAL, "d_p and d_q must not be NULL");
   if ((rc = use_device(s)) != MB4_OK) return rc;
   HIP_TRY(mb4::launch_interleave(d_p, d_q, s->u0, int(s->sites), s->stream));
-  if ((rc = clear_stats(s)) != MB4_OK) return rc;
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->steps_done = 0;
   s->predicted = kInitialPrediction;
@@ -548,10 +602,19 @@ int mb4_step(mb4_state* s, int64_t nsteps) {
   if (rc != MB4_OK) return rc;
   if (nsteps < 0) return fail(MB4_EINVAL, "nsteps must be >= 0");
   if ((rc = use_device(s)) != MB4_OK) return rc;
-  for (int64_t n = 0; n < nsteps; ++n) {
-    rc = step_once(s);
+  int64_t left = nsteps;
+  while (left > 0) {
+    const int count = int(std::min<int64_t>(left, kBatch));
+    const int iters = std::max(1, std::min(s->predicted, s->max_newton));
+    int accepted = 0;
+    rc = run_batch(s, count, iters, &accepted);
     if (rc != MB4_OK) return rc;
-    ++s->steps_done;
+    left -= accepted;
+    if (accepted < count) {
+      rc = step_single(s);
+      if (rc != MB4_OK) return rc;
+      --left;
+    }
   }
   return MB4_OK;
 }
@@ -601,8 +664,8 @@ int mb4_last_residuals(const mb4_state* s, double* out, int32_t n, int32_t* coun
   int rc = check_state(s);
   if (rc != MB4_OK) return rc;
   if (n < 0 || (n > 0 && out == nullptr)) return fail(MB4_EINVAL, "bad output buffer");
-  const int m = std::min(n, s->last_iters);
-  for (int l = 1; l <= m; ++l) out[l - 1] = bits_to_double(s->h_stats[1 + l]);
+  const int m = std::min(n, int(s->last_res.size()));
+  for (int l = 0; l < m; ++l) out[l] = s->last_res[size_t(l)];
   if (count) *count = m;
   return MB4_OK;
 }
@@ -646,10 +709,10 @@ int mb4_newton_update(mb4_state* s, double* d_U, const double* d_rbar, double* d
   const CPlanes3 uin = cplanes_of(d_U, s->sites);
   const CPlanes3 rin = has_r ? cplanes_of(d_rbar, s->sites) : CPlanes3{{nullptr, nullptr, nullptr}};
   const ConvCheck none{nullptr, 0, 0.0};
-  HIP_TRY(mb4::launch_reset_stats(s->dbg_stats, 0, s->stream));
+  HIP_TRY(mb4::launch_clear(s->dbg_rec, 2, s->stream));
   HIP_TRY(mb4::launch_update_residual(lattice_of(s), uin, P(s->Ua), rin, has_r, false,
-                                      planes_of(d_phibar, s->sites), &s->dbg_stats->rmax[0], none,
-                                      none, nullptr, s->stream));
+                                      planes_of(d_phibar, s->sites), s->dbg_rec + 1, none, none,
+                                      nullptr, s->stream));
   if (has_r) {
     // The pass cannot update U in place (other blocks read its halo), so the
     // result goes through the state's stage buffer.
@@ -658,11 +721,10 @@ int mb4_newton_update(mb4_state* s, double* d_U, const double* d_rbar, double* d
       HIP_TRY(hipMemcpyAsync(uout.s[i], s->Ua[i], s->sites * sizeof(double2),
                              hipMemcpyDeviceToDevice, s->stream));
   }
-  unsigned long long* h = s->h_stats + 2 + mb4::kMaxNewton;  // past the step statistics
-  HIP_TRY(hipMemcpyAsync(h, s->dbg_stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                         s->stream));
+  HIP_TRY(hipMemcpyAsync(s->h_dbg, s->dbg_rec, 2 * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (rnorm) *rnorm = bits_to_double(h[1]);
+  if (rnorm) *rnorm = bits_to_double(s->h_dbg[1]);
   return MB4_OK;
 }
 

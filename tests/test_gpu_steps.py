@@ -128,3 +128,51 @@ def test_zero_state_stays_zero():
     gpu, _, _, stats = _run_gpu(cfg, 3, v, z, z)
     assert np.all(gpu == 0)
     assert stats["newton_iters"] == 1
+
+
+def test_batched_steps_match_single_steps_bitwise():
+    # mb4_step enqueues many steps per host round trip; stepping one at a
+    # time must give the same bits.
+    torch_cuda()
+    cfg = L.CONFIGS["lattice32"]
+    v, p, q = L.make_inputs(cfg)
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h) as st:
+        st.set_state(p, q)
+        assert st.step(70) == M.MB4_OK
+        a = st.psi()
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h) as st:
+        st.set_state(p, q)
+        for _ in range(70):
+            assert st.step(1) == M.MB4_OK
+        b = st.psi()
+        assert st.steps_done() == 70
+    assert np.array_equal(a, b)
+
+
+def test_step_needing_more_iterations_than_predicted():
+    # A fresh state predicts 3 Newton iterations per step; at eps = 1e-15 a
+    # step needs more, so the first batch stops at its first step, the
+    # single-step path finishes it, and later batches use the new count.
+    torch_cuda()
+    cfg = L.CONFIGS["lattice32"]
+    v, p, q = L.make_inputs(cfg)
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=1e-10) as st:
+        st.set_state(p, q)
+        assert st.step(5) == M.MB4_OK
+        it_loose = st.last_stats()["newton_iters"]
+        mp, mq = st.get_state()
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=1e-15) as st:
+        st.set_state(mp, mq)
+        assert st.step(1) == M.MB4_OK
+        it_tight = st.last_stats()["newton_iters"]
+    assert it_tight > it_loose and it_tight > 3
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=1e-15) as st:
+        st.set_state(mp, mq)
+        assert st.step(40) == M.MB4_OK
+        a = st.psi()
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=1e-15) as st:
+        st.set_state(mp, mq)
+        for _ in range(40):
+            assert st.step(1) == M.MB4_OK
+        b = st.psi()
+    assert np.array_equal(a, b)
