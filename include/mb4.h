@@ -82,7 +82,13 @@ typedef struct {
   int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve; default 3, <= 64 */
   void* stream;          /* hipStream_t for all work of the state; NULL = null stream */
   uint64_t mem_budget;   /* bytes of device memory the state may allocate; 0 = no limit */
+  uint32_t flags;        /* MB4_FLAG_* bits; 0 = defaults */
 } mb4_options;
+
+/* mb4_options.flags: launch every kernel from the host instead of replaying
+ * captured HIP graphs of whole batches of steps (same results, bit for bit;
+ * graphs are never used while profiling is enabled). */
+#define MB4_FLAG_NO_GRAPHS 1u
 
 typedef struct mb4_state mb4_state;
 

@@ -90,6 +90,24 @@ hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout
                                   unsigned long long* rslot, ConvCheck check, ConvCheck fin,
                                   double2* u0_out, hipStream_t stream, LaunchEvents ev = {});
 
+// Newton iteration `iter` fused with the stage solve of iteration iter + 1:
+// unless `check` says an earlier iteration converged (then nothing) or `fin`
+// says iteration iter converged (then the final update of u0_out, as in
+// launch_update_residual), Uout <- base + (T (x) I) rbar (base = Uin, or
+// e_3 (x) u_0 if from_u0), Phibar of Uout, then `sweeps` (1..4) block-Jacobi
+// sweeps of the stage systems into rout, and ||(T (x) I) rout||_inf into
+// *rnext.  Uin/Uout and rbar/rout must not alias.
+hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
+                          Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
+                          ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
+                          LaunchEvents ev = {});
+
+// Update pass of the last iteration of a batch: the final update of u0_out if
+// `fin` holds and `check` does not; nothing otherwise.
+hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
+                               ConvCheck check, ConvCheck fin, double2* u0_out,
+                               hipStream_t stream, LaunchEvents ev = {});
+
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,
                              hipStream_t stream);

@@ -310,13 +310,10 @@ __device__ __forceinline__ double2 block_solve(const SiteBlock& s, double hl, do
                       inv * ((1.0 - hl * s.a) * bq - hl * s.cc * bp));
 }
 
-// f(u_0) = S grad H = (A q + g n q, -(A p + g n p)) at one site.
-__device__ __forceinline__ double2 f_at(const Lattice& L, int gx, int gy, double2 u, double v) {
-  const int nx = L.nx, ny = L.ny;
-  const int xl = gx == 0 ? nx - 1 : gx - 1, xr = gx == nx - 1 ? 0 : gx + 1;
-  const int yd = gy == 0 ? ny - 1 : gy - 1, yu = gy == ny - 1 ? 0 : gy + 1;
-  const double2 a = L.u0[gy * nx + xl], b = L.u0[gy * nx + xr];
-  const double2 d = L.u0[yd * nx + gx], e = L.u0[yu * nx + gx];
+// f(u_0) = S grad H = (A q + g n q, -(A p + g n p)) at one site, from u and
+// its four neighbours a, b (x -/+ 1), d, e (y -/+ 1).
+__device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v, double2 a,
+                                          double2 b, double2 d, double2 e) {
   const double sp = (a.x + b.x) + (d.x + e.x);
   const double sq = (a.y + b.y) + (d.y + e.y);
   const double vs = v + L.shift;
@@ -335,8 +332,9 @@ __device__ __forceinline__ double2 f_at(const Lattice& L, int gx, int gy, double
 // positions, two per thread, so the tile shrinks as the halo grows.
 //
 // FIRST: Newton iteration 1.  The right-hand side -Phibar_i = h TC_i f(u_0)
-// is built in place (TC = T^-1 c); ||u_0||_inf goes to *u0max_slot; with
-// store_rhs the tile's Phibar is also written out (for extra plain sweeps).
+// is built in place (TC = T^-1 c) from u_0 staged in LDS on the region plus
+// a one-site ring; ||u_0||_inf goes to *u0max_slot; with store_rhs the tile's
+// Phibar is also written out (for extra plain sweeps).
 constexpr int kRX = 64;
 constexpr int kRY = 16;
 constexpr int kSolveThreads = 512;
@@ -358,30 +356,49 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
   constexpr int TSX = solve_tile_x(H), TSY = solve_tile_y(H);
   constexpr int PER = RN / kSolveThreads;
   static_assert(RN % kSolveThreads == 0, "region must be a whole number of passes");
+  constexpr int UX = RX + 2, UN = FIRST ? UX * (RY + 2) : 1;
   __shared__ double2 sr[3][RN];
+  __shared__ double2 su[UN];
   const int nx = L.nx, ny = L.ny;
   const int tiles_x = (nx + TSX - 1) / TSX;
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int tx0 = (b % tiles_x) * TSX, ty0 = (b / tiles_x) * TSY;
 
+  // Own positions first: their potential is loaded before the u_0 staging
+  // below, so both sets of loads are in flight together.
+  int gsite[PER];
+  double vv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kSolveThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    gsite[j] = wrap(ty0 - H + ly, ny) * nx + wrap(tx0 - H + lx, nx);
+    vv[j] = L.V[gsite[j]];
+  }
+  if (FIRST) {
+    for (int e = threadIdx.x; e < UN; e += kSolveThreads) {
+      const int ex = e % UX, ey = e / UX;
+      su[e] = L.u0[wrap(ty0 - H - 1 + ey, ny) * nx + wrap(tx0 - H - 1 + ex, nx)];
+    }
+    __syncthreads();
+  }
+
   double2 rhs[PER][3];
   SiteBlock blk[PER];
   double inv[PER][3];
-  int gsite[PER];
   unsigned long long um = 0ull;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kSolveThreads;
     const int lx = idx % RX, ly = idx / RX;
-    const int gx = wrap(tx0 - H + lx, nx), gy = wrap(ty0 - H + ly, ny);
-    const int site = gy * nx + gx;
-    gsite[j] = site;
-    const double2 u = L.u0[site];
-    const double v = L.V[site];
+    const int site = gsite[j];
+    const int e = (ly + 1) * UX + lx + 1;
+    const double2 u = FIRST ? su[e] : L.u0[site];
+    const double v = vv[j];
     blk[j] = site_block(L, u, v);
     double2 f = make_double2(0.0, 0.0);
     if (FIRST) {
-      f = f_at(L, gx, gy, u, v);
+      f = f_from(L, u, v, su[e - 1], su[e + 1], su[e - UX], su[e + UX]);
       const bool out = lx >= H && lx < H + TSX && ly >= H && ly < H + TSY &&
                        tx0 + lx - H < nx && ty0 + ly - H < ny;
       if (out) um = umax(um, umax(abs_bits(u.x), abs_bits(u.y)));
@@ -463,6 +480,234 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
   }
   if (rslot != nullptr) block_max_to<kSolveThreads>(rm, rslot);
   if (FIRST) block_max_to<kSolveThreads>(um, fa.u0max_slot);
+}
+
+// ---------------------------------------------------------------------------
+// One Newton iteration's update and residual fused with the next iteration's
+// stage solve, so that Phibar never goes through HBM.  For iteration `iter`:
+//   U^iter = U^{iter-1} + (T (x) I) rbar^iter        (Eq. MB4_6; U^0 = e_3 (x) u_0)
+//   Phibar^iter = (T^-1 (x) I) Phi(U^iter)           (Eqs. Phidefinition, MB4_4)
+//   rbar^{iter+1} = H + 1 block-Jacobi sweeps on (I - h lambda_i J) r = -Phibar^iter
+//   rec[iter + 1] = ||(T (x) I) rbar^{iter+1}||_inf
+// unless iteration iter already met the tolerance, in which case the block
+// writes u_1 = U_3^{iter-1} + (T rbar^iter)_3 over u_0 for its tile (Sec. 2.2:
+// c_3 = 1) and stops.  A 512-thread block works on a 64 x 16 region, two
+// positions per thread: W_i (Eq. fKu2) on the whole region in LDS, the
+// residual on the region less one ring, the sweeps on shrinking rings, and
+// the (62 - 2H) x (14 - 2H) tile in the middle is written back.  As in
+// k_stage_solve, each region position computes the values of its (wrapped)
+// lattice site from region neighbours only.
+constexpr int kIX = 64;
+constexpr int kIY = 16;
+constexpr int kIterThreads = 512;
+__host__ __device__ constexpr int iter_tile_x(int h) { return kIX - 2 - 2 * h; }
+__host__ __device__ constexpr int iter_tile_y(int h) { return kIY - 2 - 2 * h; }
+
+template <bool FROM_U0, int H>
+__global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(Lattice L, CPlanes3 Uin,
+                                                             Planes3 Uout, CPlanes3 rb,
+                                                             Planes3 rout,
+                                                             unsigned long long* rnext,
+                                                             ConvCheck chk, ConvCheck fin,
+                                                             double2* u0_out) {
+  if (converged_at(chk)) return;
+  constexpr int RX = kIX, RY = kIY, RN = RX * RY;
+  constexpr int TSX = iter_tile_x(H), TSY = iter_tile_y(H);
+  constexpr int PER = RN / kIterThreads;
+  const int nx = L.nx, ny = L.ny;
+  const int tiles_x = (nx + TSX - 1) / TSX;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int tx0 = (b % tiles_x) * TSX, ty0 = (b / tiles_x) * TSY;
+  const int ox = tx0 - H - 1, oy = ty0 - H - 1;  // region origin
+
+  if (converged_at(fin)) {
+    // Final update on this block's tile only.
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = threadIdx.x + j * kIterThreads;
+      const int lx = idx % RX, ly = idx / RX;
+      if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY &&
+          ox + lx < nx && oy + ly < ny) {
+        const int site = (oy + ly) * nx + (ox + lx);
+        double2 r[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
+        const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
+        const double2 d = t_apply(2, r);
+        u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
+      }
+    }
+    return;
+  }
+
+  __shared__ double2 sb[3][RN];  // W_i, then the stage iterates
+  int gsite[PER];
+  double2 u0v[PER];
+  double2 Un[PER][3];
+  double vv[PER];
+  // Phase 1: U^iter and W_i on the whole region.
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kIterThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    const int site = wrap(oy + ly, ny) * nx + wrap(ox + lx, nx);
+    gsite[j] = site;
+    double2 W[3];
+    unsigned long long rm_unused;
+    site_update<FROM_U0, true>(L, Uin, rb, site, u0v[j], Un[j], W, rm_unused);
+    vv[j] = L.V[site];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) sb[i][idx] = W[i];
+  }
+  __syncthreads();
+
+  // Phase 2: residual, transform and first (local) sweep on ring >= 1.
+  double2 rhs[PER][3];
+  SiteBlock blk[PER];
+  double inv[PER][3];
+  double2 r1[PER][3];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kIterThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    blk[j] = site_block(L, u0v[j], vv[j]);
+    if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
+      const double t = L.t, g = L.g, h = L.h;
+      const double vs = vv[j] + L.shift;
+      double2 phi[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 w = sb[i][idx];
+        const double2 l = sb[i][idx - 1], r = sb[i][idx + 1];
+        const double2 d = sb[i][idx - RX], u = sb[i][idx + RX];
+        const double sp = (l.x + r.x) + (d.x + u.x);
+        const double sq = (l.y + r.y) + (d.y + u.y);
+        phi[i] = make_double2(-t * sq + vs * w.y, t * sp - vs * w.x);
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double zp = MB4_GL_L[q][0] * u0v[j].x + MB4_GL_L[q][1] * Un[j][0].x +
+                          MB4_GL_L[q][2] * Un[j][1].x + MB4_GL_L[q][3] * Un[j][2].x;
+        const double zq = MB4_GL_L[q][0] * u0v[j].y + MB4_GL_L[q][1] * Un[j][0].y +
+                          MB4_GL_L[q][2] * Un[j][1].y + MB4_GL_L[q][3] * Un[j][2].y;
+        const double gn = g * (zp * zp + zq * zq);
+        const double fp = gn * zq, fq = -gn * zp;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          phi[i].x += MB4_GL_Q[i][q] * fp;
+          phi[i].y += MB4_GL_Q[i][q] * fq;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        phi[i].x = (Un[j][i].x - u0v[j].x) - h * phi[i].x;
+        phi[i].y = (Un[j][i].y - u0v[j].y) - h * phi[i].y;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double bp = MB4_TINV[i][0] * phi[0].x + MB4_TINV[i][1] * phi[1].x +
+                          MB4_TINV[i][2] * phi[2].x;
+        const double bq = MB4_TINV[i][0] * phi[0].y + MB4_TINV[i][1] * phi[1].y +
+                          MB4_TINV[i][2] * phi[2].y;
+        const double hl = L.h * MB4_LAMBDA[i];
+        rhs[j][i] = make_double2(-bp, -bq);
+        inv[j][i] = 1.0 / (1.0 + hl * hl * (blk[j].bb * blk[j].cc - blk[j].a * blk[j].a));
+        r1[j][i] = block_solve(blk[j], hl, inv[j][i], -bp, -bq);
+      }
+    }
+  }
+  __syncthreads();  // every stencil read of W is done
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kIterThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) sb[i][idx] = r1[j][i];
+    }
+  }
+  // Sweeps 2 .. H+1 on ring >= 2, one stage at a time (see k_stage_solve).
+#pragma unroll
+  for (int s = 0; s < H; ++s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double hl = L.h * MB4_LAMBDA[i];
+      const double ht = hl * L.t;
+      __syncthreads();
+      double2 rn[PER];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = threadIdx.x + j * kIterThreads;
+        const int lx = idx % RX, ly = idx / RX;
+        if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) {
+          const double2 q1 = sb[i][idx - 1], q2 = sb[i][idx + 1];
+          const double2 q3 = sb[i][idx - RX], q4 = sb[i][idx + RX];
+          const double sp = (q1.x + q2.x) + (q3.x + q4.x);
+          const double sq = (q1.y + q2.y) + (q3.y + q4.y);
+          rn[j] = block_solve(blk[j], hl, inv[j][i], rhs[j][i].x - ht * sq,
+                              rhs[j][i].y + ht * sp);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = threadIdx.x + j * kIterThreads;
+        const int lx = idx % RX, ly = idx / RX;
+        if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) sb[i][idx] = rn[j];
+      }
+    }
+  }
+  __syncthreads();
+  // The tile: U^iter and rbar^{iter+1} back to HBM, and the update norm.
+  unsigned long long rm = 0ull;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kIterThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY && ox + lx < nx &&
+        oy + ly < ny) {
+      const int site = gsite[j];
+      double2 r[3], rp[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        r[i] = sb[i][idx];
+        rout.s[i][site] = r[i];
+        rp[i] = rb.s[i][site];
+      }
+      // U^iter again from its inputs (cheaper than keeping it live in
+      // registers across the sweeps).
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 base = FROM_U0 ? L.u0[site] : Uin.s[i][site];
+        const double2 d = t_apply(i, rp);
+        Uout.s[i][site] = make_double2(base.x + d.x, base.y + d.y);
+      }
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double2 d = t_apply(m, r);
+        rm = umax(rm, umax(abs_bits(d.x), abs_bits(d.y)));
+      }
+    }
+  }
+  block_max_to<kIterThreads>(rm, rnext);
+}
+
+// Update pass of the last Newton iteration `fin.prev` of a batch: the final
+// update u_1 = U_3 + (T rbar)_3 (base U_3 = Uin[2], or u_0 if from_u0) if that
+// iteration met the tolerance and none before it did; nothing otherwise.
+template <bool FROM_U0>
+__global__ __launch_bounds__(256) void k_final_update(Lattice L, CPlanes3 Uin, CPlanes3 rb,
+                                                      ConvCheck chk, ConvCheck fin,
+                                                      double2* u0_out, int n) {
+  if (converged_at(chk) || !converged_at(fin)) return;
+  const int site = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (site >= n) return;
+  double2 r[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
+  const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
+  const double2 d = t_apply(2, r);
+  u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
 }
 
 // One more block-Jacobi sweep from the iterate rin (solves with more than
@@ -620,13 +865,17 @@ int solve_blocks(int nx, int ny, int h) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Every launch goes through hipExtLaunchKernelGGL so that, when the runtime
-// asks for timing, the start/stop timestamps are taken by the dispatch itself
-// (no extra marker packets between kernels).
+// A timed launch goes through hipExtLaunchKernelGGL, so that the start/stop
+// timestamps are taken by the dispatch itself (no extra marker packets
+// between kernels); an untimed one is a plain launch (which stream capture
+// into graphs records as a kernel node).
 #define MB4_LAUNCH(kernel, grid, block, ev, ...)                                             \
   do {                                                                                       \
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, (ev).start, (ev).stop, 0u,        \
-                          __VA_ARGS__);                                                      \
+    if ((ev).start == nullptr && (ev).stop == nullptr)                                       \
+      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                       \
+    else                                                                                     \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, (ev).start, (ev).stop, 0u,      \
+                            __VA_ARGS__);                                                    \
     return hipGetLastError();                                                                \
   } while (0)
 
@@ -708,6 +957,46 @@ hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, P
                               LaunchEvents ev) {
   MB4_LAUNCH(k_stage_sweep, dim3(tile_blocks(lat.nx, lat.ny)), dim3(kTile), ev, lat, phib, rin,
              rout, rslot, check);
+}
+
+hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
+                          Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
+                          ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
+                          LaunchEvents ev) {
+  const int h = sweeps - 1;
+  if (h < 0 || h > 3) return hipErrorInvalidValue;
+  const int tx = iter_tile_x(h), ty = iter_tile_y(h);
+  const dim3 grid(((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)), block(kIterThreads);
+#define MB4_ITER_CASE(F, HH)                                                                 \
+  MB4_LAUNCH((k_iterate<F, HH>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext, check, \
+             fin, u0_out)
+  if (from_u0) {
+    switch (h) {
+      case 0: MB4_ITER_CASE(true, 0);
+      case 1: MB4_ITER_CASE(true, 1);
+      case 2: MB4_ITER_CASE(true, 2);
+      default: MB4_ITER_CASE(true, 3);
+    }
+  } else {
+    switch (h) {
+      case 0: MB4_ITER_CASE(false, 0);
+      case 1: MB4_ITER_CASE(false, 1);
+      case 2: MB4_ITER_CASE(false, 2);
+      default: MB4_ITER_CASE(false, 3);
+    }
+  }
+#undef MB4_ITER_CASE
+}
+
+hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
+                               ConvCheck check, ConvCheck fin, double2* u0_out,
+                               hipStream_t stream, LaunchEvents ev) {
+  const int n = lat.nx * lat.ny;
+  const dim3 grid((n + 255) / 256), block(256);
+  if (from_u0)
+    MB4_LAUNCH(k_final_update<true>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n);
+  else
+    MB4_LAUNCH(k_final_update<false>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n);
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -85,6 +85,19 @@ struct mb4_state {
   int max_newton = kDefaultMaxNewton;
   int sweeps = kDefaultSweeps;
   hipStream_t stream = nullptr;
+  // Stream the step kernels are enqueued to: `stream`, or cap_stream while a
+  // batch is being captured into a graph.
+  hipStream_t q = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool use_graphs = true;
+  // Instantiated graphs of whole batches, keyed by (steps, iterations); the
+  // time step and buffers are baked into their kernel arguments, so
+  // mb4_set_h drops them.
+  struct GraphEntry {
+    int count, iters;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
   int device = 0;
   std::vector<void*> device_allocs;
   std::vector<void*> host_allocs;
@@ -118,8 +131,8 @@ struct mb4_state {
     hipEvent_t a, b;
   };
   std::vector<Rec> prof_pending;
-  int64_t prof_launches[6] = {0, 0, 0, 0, 0, 0};
-  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t steps_done = 0;
   int last_iters = 0;
   int last_sweeps = 0;
@@ -158,7 +171,15 @@ int halloc(mb4_state* s, void** p, size_t bytes) {
   return MB4_OK;
 }
 
+void drop_graphs(mb4_state* s) {
+  for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+}
+
 void free_all(mb4_state* s) {
+  drop_graphs(s);
+  if (s->cap_stream != nullptr) (void)hipStreamDestroy(s->cap_stream);
+  s->cap_stream = nullptr;
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   s->ev_pool.clear();
   for (void* p : s->device_allocs) (void)hipFree(p);
@@ -207,12 +228,15 @@ enum KernelClass {
   kSweep = 2,
   kUpdateResidualFirst = 3,
   kUpdateResidual = 4,
-  kFinalUpdate = 5
+  kFinalUpdate = 5,
+  kIterateFirst = 6,
+  kIterate = 7,
+  kFinalEnd = 8,  // recorded as such, counted as kFinalUpdate
 };
-constexpr int kKernelClasses = 6;
-const char* const kKernelNames[kKernelClasses] = {"stage_solve_first", "stage_solve",
-                                                  "stage_sweep", "update_residual_first",
-                                                  "update_residual", "final_update"};
+constexpr int kKernelClasses = 8;
+const char* const kKernelNames[kKernelClasses] = {
+    "stage_solve_first", "stage_solve", "stage_sweep", "update_residual_first",
+    "update_residual",   "final_update", "iterate_first", "iterate"};
 
 int prof_event(mb4_state* s, hipEvent_t* ev) {
   if (s->ev_used == s->ev_pool.size()) {
@@ -235,11 +259,14 @@ int prof_collect(mb4_state* s, const std::vector<int>& m) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
     int cls = r.cls;
-    if (cls == kUpdateResidual) {
+    if (cls == kUpdateResidual || cls == kIterate) {
       if (r.iter == mk)
         cls = kFinalUpdate;
       else if (r.iter == 1)
-        cls = kUpdateResidualFirst;
+        cls = cls == kUpdateResidual ? kUpdateResidualFirst : kIterateFirst;
+    } else if (cls == kFinalEnd) {
+      if (r.iter != mk) continue;  // returned at once
+      cls = kFinalUpdate;
     }
     s->prof_launches[cls] += 1;
     s->prof_ms[cls] += ms;
@@ -286,11 +313,11 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
     const Planes3 store = extra ? P(s->phib) : Planes3{{nullptr, nullptr, nullptr}};
     LAUNCH(s, kFirstSolve, step, iter,
            mb4::launch_first_solve(L, P(s->ra), fused, extra ? nullptr : rslot, rec, store,
-                                   s->stream, ev_));
+                                   s->q, ev_));
   } else {
     LAUNCH(s, kStageSolve, step, iter,
            mb4::launch_stage_solve(L, C(s->phib), P(s->ra), fused, extra ? nullptr : rslot, chk,
-                                   s->stream, ev_));
+                                   s->q, ev_));
   }
   double2* const* cur = s->ra;
   for (int k = fused; k < s->sweeps; ++k) {
@@ -298,10 +325,49 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
     const CPlanes3 in{{cur[0], cur[1], cur[2]}};
     LAUNCH(s, kSweep, step, iter,
            mb4::launch_stage_sweep(L, C(s->phib), in, P(out),
-                                   k == s->sweeps - 1 ? rslot : nullptr, chk, s->stream, ev_));
+                                   k == s->sweeps - 1 ? rslot : nullptr, chk, s->q, ev_));
     cur = out;
   }
   *result = cur;
+  return MB4_OK;
+}
+
+// Newton iterate U^j lives in Ua (j odd) or Ub (j even); the stage solution
+// rbar^l of iteration l in ra (l odd) or rb (l even) on the fused path.
+double2* const* u_planes(mb4_state* s, int j) { return (j % 2 == 1) ? s->Ua : s->Ub; }
+double2* const* r_planes(mb4_state* s, int l) { return (l % 2 == 1) ? s->ra : s->rb; }
+CPlanes3 cp(double2* const* a) { return CPlanes3{{a[0], a[1], a[2]}}; }
+Planes3 pp(double2* const* a) { return Planes3{{a[0], a[1], a[2]}}; }
+
+// Fused path (at most four sweeps): iteration l's stage solve is enqueued as
+// part of the pass that updates iteration l - 1 (k_iterate), iteration 1's by
+// the first-solve kernel; after iteration `last` a final-update pass writes
+// u_1 over u_0 if `last` is where the step converged.
+int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
+                             int first, int last) {
+  for (int l = first; l <= last; ++l) {
+    if (l == 1) {
+      LAUNCH(s, kFirstSolve, step, 1,
+             mb4::launch_first_solve(L, pp(r_planes(s, 1)), s->sweeps, rec + 1, rec,
+                                     Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_));
+      continue;
+    }
+    const int j = l - 1;  // the iteration this pass updates
+    const ConvCheck chk = j >= 2 ? ConvCheck{rec, j - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+    const ConvCheck fin{rec, j, s->eps};
+    const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
+    LAUNCH(s, kIterate, step, j,
+           mb4::launch_iterate(L, uin, pp(u_planes(s, j)), cp(r_planes(s, j)),
+                               pp(r_planes(s, l)), j == 1, s->sweeps, rec + l, chk, fin, s->u0,
+                               s->q, ev_));
+  }
+  const int j = last;
+  const ConvCheck chk = j >= 2 ? ConvCheck{rec, j - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+  const ConvCheck fin{rec, j, s->eps};
+  const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
+  LAUNCH(s, kFinalEnd, step, j,
+         mb4::launch_final_update(L, uin, cp(r_planes(s, j)), j == 1, chk, fin, s->u0, s->q,
+                                  ev_));
   return MB4_OK;
 }
 
@@ -310,6 +376,8 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
 // u_1 = U_{c_3} over u_0; kernels of later iterations return at once.
 int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
                        int first, int last) {
+  if (s->sweeps <= mb4::kMaxFusedSweeps)
+    return enqueue_iterations_fused(s, L, step, rec, first, last);
   for (int l = first; l <= last; ++l) {
     double2* const* rfin = nullptr;
     const int rc = enqueue_solve(s, L, step, l, rec, &rfin);
@@ -322,7 +390,7 @@ int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long l
     const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
     LAUNCH(s, kUpdateResidual, step, l,
            mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
-                                       nullptr, chk, fin, s->u0, s->stream, ev_));
+                                       nullptr, chk, fin, s->u0, s->q, ev_));
   }
   return MB4_OK;
 }
@@ -356,14 +424,68 @@ void accept(mb4_state* s, const unsigned long long* hrec, int m) {
 // batch repeated step k's computation exactly (every kernel is
 // deterministic) and changed nothing; *accepted = k tells the caller where to
 // continue.
-int run_batch(mb4_state* s, int count, int iters, int* accepted) {
+// Enqueues the whole batch (statistics cleared, then every step) on s->q.
+int enqueue_batch(mb4_state* s, int count, int iters) {
   const Lattice L = lattice_of(s);
-  const int words = count * s->rec_len;
-  HIP_TRY(mb4::launch_clear(s->ring, words, s->stream));
+  HIP_TRY(mb4::launch_clear(s->ring, count * s->rec_len, s->q));
   for (int k = 0; k < count; ++k) {
     const int rc = enqueue_iterations(s, L, k, s->ring + size_t(k) * s->rec_len, 1, iters);
     if (rc != MB4_OK) return rc;
   }
+  return MB4_OK;
+}
+
+// The graph of a batch of `count` steps with `iters` iterations each,
+// captured on first use.
+int batch_graph(mb4_state* s, int count, int iters, hipGraphExec_t* exec) {
+  for (const auto& g : s->graphs)
+    if (g.count == count && g.iters == iters) {
+      *exec = g.exec;
+      return MB4_OK;
+    }
+  if (s->cap_stream == nullptr)
+    HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  s->q = s->cap_stream;
+  HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue_batch(s, count, iters);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+  s->q = s->stream;
+  if (rc != MB4_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(MB4_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(MB4_EDEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+  if (s->graphs.size() >= 64) {  // keep the cache bounded
+    (void)hipGraphExecDestroy(s->graphs.front().exec);
+    s->graphs.erase(s->graphs.begin());
+  }
+  s->graphs.push_back(mb4_state::GraphEntry{count, iters, ex});
+  *exec = ex;
+  return MB4_OK;
+}
+
+int run_batch(mb4_state* s, int count, int iters, int* accepted) {
+  // Graphs replay the same launches with less host work per kernel; while
+  // profiling, kernels are launched one by one with their timing events.
+  hipGraphExec_t exec = nullptr;
+  if (s->use_graphs && !s->prof_on && batch_graph(s, count, iters, &exec) != MB4_OK) {
+    // A runtime that cannot capture these launches: run eagerly from now on.
+    (void)hipGetLastError();
+    s->use_graphs = false;
+    exec = nullptr;
+  }
+  if (exec != nullptr) {
+    HIP_TRY(hipGraphLaunch(exec, s->stream));
+  } else {
+    const int rc = enqueue_batch(s, count, iters);
+    if (rc != MB4_OK) return rc;
+  }
+  const int words = count * s->rec_len;
   HIP_TRY(hipMemcpyAsync(s->h_ring, s->ring, sizeof(unsigned long long) * words,
                          hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -385,7 +507,7 @@ int run_batch(mb4_state* s, int count, int iters, int* accepted) {
 int step_single(mb4_state* s) {
   const Lattice L = lattice_of(s);
   unsigned long long* rec = s->ring;
-  HIP_TRY(mb4::launch_clear(rec, s->rec_len, s->stream));
+  HIP_TRY(mb4::launch_clear(rec, s->rec_len, s->q));
   int done = 0;
   int batch = std::max(1, std::min(s->predicted + 1, s->max_newton));
   for (;;) {
@@ -465,6 +587,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     if (opt->inner_sweeps > 0) o.inner_sweeps = opt->inner_sweeps;
     o.stream = opt->stream;
     o.mem_budget = opt->mem_budget;
+    o.flags = opt->flags;
   }
   if (!all_finite(potential, size_t(sites)))
     return fail(MB4_EINVAL, "potential has non-finite entries");
@@ -486,6 +609,8 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   s->max_newton = o.max_newton;
   s->sweeps = o.inner_sweeps;
   s->stream = static_cast<hipStream_t>(o.stream);
+  s->q = s->stream;
+  s->use_graphs = (o.flags & MB4_FLAG_NO_GRAPHS) == 0;
 
   int rc = MB4_OK;
   hipError_t e = hipGetDevice(&s->device);
@@ -644,6 +769,7 @@ int mb4_set_h(mb4_state* s, double h) {
   int rc = check_state(s);
   if (rc != MB4_OK) return rc;
   if (!isfinite(h) || h == 0.0) return fail(MB4_EINVAL, "h must be finite and non-zero");
+  if (h != s->h) drop_graphs(s);
   s->h = h;
   return MB4_OK;
 }

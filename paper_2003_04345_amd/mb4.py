@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_int, c_int32,
-                    c_int64, c_uint64, c_void_p)
+                    c_int64, c_uint32, c_uint64, c_void_p)
 
 import numpy as np
 
@@ -33,7 +33,10 @@ class mb4_nonlinearity(Structure):
 
 class mb4_options(Structure):
     _fields_ = [("eps", c_double), ("max_newton", c_int32), ("inner_sweeps", c_int32),
-                ("stream", c_void_p), ("mem_budget", c_uint64)]
+                ("stream", c_void_p), ("mem_budget", c_uint64), ("flags", c_uint32)]
+
+
+MB4_FLAG_NO_GRAPHS = 1
 
 
 class Mb4Error(RuntimeError):
@@ -243,7 +246,8 @@ class MB4State:
 
     def __init__(self, nx: int, ny: int, potential, g: float, h: float, t_hop: float = 1.0,
                  diag_shift: float = 0.0, eps: float = 0.0, max_newton: int = 0,
-                 inner_sweeps: int = 0, stream: int | None = None, mem_budget: int = 0):
+                 inner_sweeps: int = 0, stream: int | None = None, mem_budget: int = 0,
+                 graphs: bool = True):
         self.nx, self.ny = int(nx), int(ny)
         self.sites = self.nx * self.ny
         opt = mb4_options_default()
@@ -255,6 +259,7 @@ class MB4State:
             opt.inner_sweeps = inner_sweeps
         opt.stream = stream
         opt.mem_budget = mem_budget
+        opt.flags = 0 if graphs else MB4_FLAG_NO_GRAPHS
         self._h = mb4_create(mb4_lattice(self.nx, self.ny, t_hop, diag_shift), potential,
                              mb4_nonlinearity(g), h, opt)
 

@@ -61,9 +61,9 @@ def test_struct_layout_matches_binding():
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(mb4_lattice), offsetof(mb4_lattice, t_hop),
          offsetof(mb4_lattice, diag_shift), sizeof(mb4_nonlinearity));
-  printf("%zu %zu %zu %zu %zu\n", sizeof(mb4_options), offsetof(mb4_options, max_newton),
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mb4_options), offsetof(mb4_options, max_newton),
          offsetof(mb4_options, inner_sweeps), offsetof(mb4_options, stream),
-         offsetof(mb4_options, mem_budget));
+         offsetof(mb4_options, mem_budget), offsetof(mb4_options, flags));
   return 0;
 }
 '''
@@ -80,7 +80,7 @@ int main(void) {
                  M.mb4_lattice.diag_shift.offset, ctypes.sizeof(M.mb4_nonlinearity)]
     assert b == [ctypes.sizeof(M.mb4_options), M.mb4_options.max_newton.offset,
                  M.mb4_options.inner_sweeps.offset, M.mb4_options.stream.offset,
-                 M.mb4_options.mem_budget.offset]
+                 M.mb4_options.mem_budget.offset, M.mb4_options.flags.offset]
 
 
 def _create(lat=None, v=None, g=1.0, h=0.01, opt=None):
@@ -151,7 +151,7 @@ def test_null_arguments(lib):
 def test_options_default_values(lib):
     o = M.mb4_options_default()
     assert o.eps == 1e-13 and o.max_newton == 50 and o.inner_sweeps == 3
-    assert o.stream is None and o.mem_budget == 0
+    assert o.stream is None and o.mem_budget == 0 and o.flags == 0
 
 
 def test_strerror_covers_codes(lib):
