@@ -76,8 +76,9 @@ typedef struct {
 /* Solver options; pass NULL for all defaults, or start from
  * mb4_options_default().  Zero in a numeric field selects its default. */
 typedef struct {
-  double eps;            /* Newton tolerance relative to ||u_0||_inf; default 1e-13
-                            (the paper's epsilon, Sec. 3, read as relative) */
+  double eps;            /* Newton tolerance: the loop stops once ||r^l||_inf <= eps
+                            (Algorithm 1; default 1e-13, the epsilon of Sec. 3),
+                            or <= eps * ||u_0||_inf with MB4_FLAG_RELATIVE_EPS */
   int32_t max_newton;    /* Newton iterations before MB4_ENOCONV; default 50, <= 1000 */
   int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve; default 3, <= 64 */
   void* stream;          /* hipStream_t for all work of the state; NULL = null stream */
@@ -89,6 +90,9 @@ typedef struct {
  * captured HIP graphs of whole batches of steps (same results, bit for bit;
  * graphs are never used while profiling is enabled). */
 #define MB4_FLAG_NO_GRAPHS 1u
+/* mb4_options.flags: read eps relative to ||u_0||_inf of each step instead of
+ * as an absolute bound (for states whose amplitude is far from 1). */
+#define MB4_FLAG_RELATIVE_EPS 2u
 
 typedef struct mb4_state mb4_state;
 

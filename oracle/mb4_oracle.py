@@ -32,8 +32,10 @@ are reported in the library's convention H = (U_K + U_I + U_E) / 2, i.e. half
 the paper's H, so that the flow reads u' = S grad H with S = [[0, I], [-I, 0]].
 
 Readings of points the paper leaves open (each one listed in the design
-notes): the Newton stopping test is relative, ||r||_inf <= eps * ||u_0||_inf;
-the initial Newton guess is e_3 (x) u_0; eigenvalues are sorted ascending.
+notes): the Newton loop stops once ||r^l||_inf <= eps, an absolute bound as in
+Algorithm 1 (eps = 1e-13 in Sec. 3), or, with relative=True, once
+||r^l||_inf <= eps * ||u_0||_inf; the initial Newton guess is e_3 (x) u_0;
+eigenvalues are sorted ascending.
 """
 from __future__ import annotations
 
@@ -261,10 +263,11 @@ class MB4Oracle:
 
     def __init__(self, problem: LatticeNLS, h: float, eps: float = EPS_PAPER,
                  max_newton: int = 50, constants: MB4Constants | None = None,
-                 solver: str = "direct", gmres_rtol: float = 1e-14):
+                 solver: str = "direct", gmres_rtol: float = 1e-14, relative: bool = False):
         self.prob = problem
         self.h = float(h)
         self.eps = float(eps)
+        self.relative = bool(relative)
         self.max_newton = int(max_newton)
         self.k = constants if constants is not None else method_constants()
         self.solver = solver
@@ -323,9 +326,13 @@ class MB4Oracle:
         s = self.prob.s
         solves = self._stage_solvers(u0)             # J frozen at u_0 (Eq. Jacobian2)
         U = np.stack([u0, u0, u0]).astype(np.complex128)   # U^0 = e_3 (x) u_0
-        scale = max(float(np.max(np.abs(u0.real), initial=0.0)),
-                    float(np.max(np.abs(u0.imag), initial=0.0)))
-        tol = self.eps * max(scale, np.finfo(np.float64).tiny)
+        # Stopping test of Algorithm 1: ||r^l||_inf against eps, absolute
+        # unless a bound relative to ||u_0||_inf was asked for.
+        tol = self.eps
+        if self.relative:
+            scale = max(float(np.max(np.abs(u0.real), initial=0.0)),
+                        float(np.max(np.abs(u0.imag), initial=0.0)))
+            tol = self.eps * max(scale, np.finfo(np.float64).tiny)
         r = math.inf
         it = 0
         T, Tinv = self.k.T, self.k.Tinv
@@ -370,9 +377,9 @@ def energy_drift(energies) -> float:
 
 
 def oracle_for(prob_cfg, potential, eps=EPS_PAPER, max_newton=50, solver="direct",
-               constants=None) -> MB4Oracle:
+               constants=None, relative=False) -> MB4Oracle:
     """Oracle for a lattice_inputs.LatticeProblem-like object."""
     lat = LatticeNLS(prob_cfg.nx, prob_cfg.ny, potential, prob_cfg.g,
                      t_hop=prob_cfg.t_hop, diag_shift=prob_cfg.diag_shift)
     return MB4Oracle(lat, prob_cfg.h, eps=eps, max_newton=max_newton,
-                     solver=solver, constants=constants)
+                     solver=solver, constants=constants, relative=relative)

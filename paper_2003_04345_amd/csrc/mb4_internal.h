@@ -40,7 +40,8 @@ struct CPlanes3 {
 struct ConvCheck {
   const unsigned long long* rec;  // step record; NULL: the test is false
   int prev;                       // iteration whose norm decides
-  double eps;
+  double eps;                     // ||r^prev||_inf <= eps (Algorithm 1) ...
+  bool relative;                  // ... or <= eps * ||u_0||_inf (rec[0])
 };
 
 // Optional timestamps of one launch (both NULL: untimed).

@@ -77,9 +77,8 @@ __device__ __forceinline__ double conv_tol(double eps, double u0max) {
 // True when Newton iteration c.prev (>= 1) already met the tolerance.
 __device__ __forceinline__ bool converged_at(const ConvCheck& c) {
   if (c.rec == nullptr) return false;
-  const double u0max = bits_double(c.rec[0]);
   const double r = bits_double(c.rec[c.prev]);
-  return r <= conv_tol(c.eps, u0max);
+  return r <= (c.relative ? conv_tol(c.eps, bits_double(c.rec[0])) : c.eps);
 }
 
 // Block-wide max of v posted to *slot.  Device-scope atomics on one address
@@ -328,15 +327,15 @@ __device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v,
 // shrinking by one ring per sweep, and only the tile's interior goes back to
 // HBM.  Each region position computes the iterate of its (wrapped) lattice
 // site from its own region neighbours, so lattices smaller than the region
-// give the same values as large ones.  The region is always 64 x 16 = 1024
+// give the same values as large ones.  The region is always 32 x 32 = 1024
 // positions, two per thread, so the tile shrinks as the halo grows.
 //
 // FIRST: Newton iteration 1.  The right-hand side -Phibar_i = h TC_i f(u_0)
 // is built in place (TC = T^-1 c) from u_0 staged in LDS on the region plus
 // a one-site ring; ||u_0||_inf goes to *u0max_slot; with store_rhs the tile's
 // Phibar is also written out (for extra plain sweeps).
-constexpr int kRX = 64;
-constexpr int kRY = 16;
+constexpr int kRX = 32;
+constexpr int kRY = 32;
 constexpr int kSolveThreads = 512;
 __host__ __device__ constexpr int solve_tile_x(int h) { return kRX - 2 * h; }
 __host__ __device__ constexpr int solve_tile_y(int h) { return kRY - 2 * h; }
@@ -418,9 +417,11 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
     }
   }
   // Sweeps 2 .. H+1, one stage at a time so that only one stage's new values
-  // are live in registers: compute stage i from LDS, barrier, store it, and
-  // go on with stage i+1 (whose buffer nobody writes meanwhile).  The barrier
-  // before each compute orders it after the previous store of that buffer.
+  // are live in registers.  One barrier per stage sweep: after it, the
+  // previous stage's new values are stored (every read of that buffer is
+  // done) and stage i is computed from LDS (its buffer was last stored before
+  // at least one earlier barrier).
+  double2 rn[PER];
 #pragma unroll
   for (int s = 0; s < H; ++s) {
 #pragma unroll
@@ -428,7 +429,15 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
       const double hl = L.h * MB4_LAMBDA[i];
       const double ht = hl * L.t;
       __syncthreads();
-      double2 rn[PER];
+      if (s > 0 || i > 0) {
+        const int ip = i == 0 ? 2 : i - 1;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int idx = threadIdx.x + j * kSolveThreads;
+          const int lx = idx % RX, ly = idx / RX;
+          if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) sr[ip][idx] = rn[j];
+        }
+      }
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int idx = threadIdx.x + j * kSolveThreads;
@@ -442,13 +451,15 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
                               rhs[j][i].y + ht * sp);
         }
       }
-      __syncthreads();
+    }
+  }
+  if (H > 0) {
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        const int idx = threadIdx.x + j * kSolveThreads;
-        const int lx = idx % RX, ly = idx / RX;
-        if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) sr[i][idx] = rn[j];
-      }
+    for (int j = 0; j < PER; ++j) {
+      const int idx = threadIdx.x + j * kSolveThreads;
+      const int lx = idx % RX, ly = idx / RX;
+      if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) sr[2][idx] = rn[j];
     }
   }
   __syncthreads();
@@ -491,14 +502,14 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
 //   rec[iter + 1] = ||(T (x) I) rbar^{iter+1}||_inf
 // unless iteration iter already met the tolerance, in which case the block
 // writes u_1 = U_3^{iter-1} + (T rbar^iter)_3 over u_0 for its tile (Sec. 2.2:
-// c_3 = 1) and stops.  A 512-thread block works on a 64 x 16 region, two
+// c_3 = 1) and stops.  A 512-thread block works on a 32 x 32 region, two
 // positions per thread: W_i (Eq. fKu2) on the whole region in LDS, the
 // residual on the region less one ring, the sweeps on shrinking rings, and
-// the (62 - 2H) x (14 - 2H) tile in the middle is written back.  As in
+// the (30 - 2H) x (30 - 2H) tile in the middle is written back.  As in
 // k_stage_solve, each region position computes the values of its (wrapped)
 // lattice site from region neighbours only.
-constexpr int kIX = 64;
-constexpr int kIY = 16;
+constexpr int kIX = 32;
+constexpr int kIY = 32;
 constexpr int kIterThreads = 512;
 __host__ __device__ constexpr int iter_tile_x(int h) { return kIX - 2 - 2 * h; }
 __host__ __device__ constexpr int iter_tile_y(int h) { return kIY - 2 - 2 * h; }
@@ -626,7 +637,9 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
       for (int i = 0; i < 3; ++i) sb[i][idx] = r1[j][i];
     }
   }
-  // Sweeps 2 .. H+1 on ring >= 2, one stage at a time (see k_stage_solve).
+  // Sweeps 2 .. H+1 on ring >= 2, one stage at a time with one barrier per
+  // stage sweep (see k_stage_solve).
+  double2 rn[PER];
 #pragma unroll
   for (int s = 0; s < H; ++s) {
 #pragma unroll
@@ -634,7 +647,15 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
       const double hl = L.h * MB4_LAMBDA[i];
       const double ht = hl * L.t;
       __syncthreads();
-      double2 rn[PER];
+      if (s > 0 || i > 0) {
+        const int ip = i == 0 ? 2 : i - 1;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int idx = threadIdx.x + j * kIterThreads;
+          const int lx = idx % RX, ly = idx / RX;
+          if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) sb[ip][idx] = rn[j];
+        }
+      }
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int idx = threadIdx.x + j * kIterThreads;
@@ -648,13 +669,15 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
                               rhs[j][i].y + ht * sp);
         }
       }
-      __syncthreads();
+    }
+  }
+  if (H > 0) {
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        const int idx = threadIdx.x + j * kIterThreads;
-        const int lx = idx % RX, ly = idx / RX;
-        if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) sb[i][idx] = rn[j];
-      }
+    for (int j = 0; j < PER; ++j) {
+      const int idx = threadIdx.x + j * kIterThreads;
+      const int lx = idx % RX, ly = idx / RX;
+      if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) sb[2][idx] = rn[j];
     }
   }
   __syncthreads();
@@ -933,7 +956,7 @@ hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
   const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
   const CPlanes3 none{{nullptr, nullptr, nullptr}};
   const FirstArgs fa{u0max_slot, phib_out.s[0] != nullptr};
-  const ConvCheck nochk{nullptr, 0, 0.0};
+  const ConvCheck nochk{nullptr, 0, 0.0, false};
   switch (sweeps) {
     case 1:
       MB4_LAUNCH((k_stage_solve<0, true>), grid, block, ev, lat, none, phib_out, rout, rslot,

@@ -67,7 +67,6 @@ bool all_finite(const double* v, size_t n) {
   return true;
 }
 
-double conv_tol(double eps, double u0max) { return eps * (u0max > DBL_MIN ? u0max : DBL_MIN); }
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -82,6 +81,7 @@ struct mb4_state {
   size_t sites = 0;
   double t = 0, shift = 0, g = 0, h = 0;
   double eps = kDefaultEps;
+  bool relative_eps = false;  // eps scaled by ||u_0||_inf
   int max_newton = kDefaultMaxNewton;
   int sweeps = kDefaultSweeps;
   hipStream_t stream = nullptr;
@@ -138,9 +138,16 @@ struct mb4_state {
   int last_sweeps = 0;
   double last_rnorm = 0.0;
   int predicted = kInitialPrediction;
+  int lower_batches = 0;  // batches in a row whose largest count was below it
 };
 
 namespace {
+
+// Device-side test "Newton iteration `prev` of the step recorded at `rec`
+// met the tolerance".
+ConvCheck conv_check(const mb4_state* s, const unsigned long long* rec, int prev) {
+  return ConvCheck{rec, prev, s->eps, s->relative_eps};
+}
 
 // Device bytes of a state: V (8 B/site), u_0 (16), two stage-value fields
 // (2 x 48), the transformed residual (48), two stage-correction fields
@@ -305,7 +312,7 @@ int launch_events(mb4_state* s, int cls, int step, int iter, mb4::LaunchEvents* 
 // rec[iter].  `*result` receives the planes that hold the solution.
 int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned long long* rec,
                   double2* const** result) {
-  const ConvCheck chk = iter >= 2 ? ConvCheck{rec, iter - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
+  const ConvCheck chk = iter >= 2 ? conv_check(s, rec, iter - 1) : ConvCheck{nullptr, 0, 0.0, false};
   const int fused = std::min(s->sweeps, mb4::kMaxFusedSweeps);
   const bool extra = s->sweeps > fused;
   unsigned long long* rslot = rec + iter;
@@ -353,8 +360,8 @@ int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned 
       continue;
     }
     const int j = l - 1;  // the iteration this pass updates
-    const ConvCheck chk = j >= 2 ? ConvCheck{rec, j - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
-    const ConvCheck fin{rec, j, s->eps};
+    const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
+    const ConvCheck fin = conv_check(s, rec, j);
     const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
     LAUNCH(s, kIterate, step, j,
            mb4::launch_iterate(L, uin, pp(u_planes(s, j)), cp(r_planes(s, j)),
@@ -362,8 +369,8 @@ int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned 
                                s->q, ev_));
   }
   const int j = last;
-  const ConvCheck chk = j >= 2 ? ConvCheck{rec, j - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
-  const ConvCheck fin{rec, j, s->eps};
+  const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
+  const ConvCheck fin = conv_check(s, rec, j);
   const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
   LAUNCH(s, kFinalEnd, step, j,
          mb4::launch_final_update(L, uin, cp(r_planes(s, j)), j == 1, chk, fin, s->u0, s->q,
@@ -382,8 +389,8 @@ int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long l
     double2* const* rfin = nullptr;
     const int rc = enqueue_solve(s, L, step, l, rec, &rfin);
     if (rc != MB4_OK) return rc;
-    const ConvCheck chk = (l >= 2) ? ConvCheck{rec, l - 1, s->eps} : ConvCheck{nullptr, 0, 0.0};
-    const ConvCheck fin{rec, l, s->eps};
+    const ConvCheck chk = (l >= 2) ? conv_check(s, rec, l - 1) : ConvCheck{nullptr, 0, 0.0, false};
+    const ConvCheck fin = conv_check(s, rec, l);
     // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
     double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
     double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
@@ -395,10 +402,17 @@ int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long l
   return MB4_OK;
 }
 
+// Newton tolerance of a step whose record starts with ||u_0||_inf bits.
+double conv_tol(const mb4_state* s, unsigned long long u0max_bits) {
+  if (!s->relative_eps) return s->eps;
+  const double u0max = bits_to_double(u0max_bits);
+  return s->eps * (u0max > DBL_MIN ? u0max : DBL_MIN);
+}
+
 // First iteration <= last whose norm in host record hrec met the tolerance;
 // 0 if none; -1 if a norm up to `last` is not finite.
 int converged_iteration(const mb4_state* s, const unsigned long long* hrec, int last) {
-  const double tol = conv_tol(s->eps, bits_to_double(hrec[0]));
+  const double tol = conv_tol(s, hrec[0]);
   for (int l = 1; l <= last; ++l) {
     const double r = bits_to_double(hrec[l]);
     if (r <= tol) return l;
@@ -413,8 +427,22 @@ void accept(mb4_state* s, const unsigned long long* hrec, int m) {
   s->last_rnorm = bits_to_double(hrec[m]);
   s->last_res.assign(size_t(m), 0.0);
   for (int l = 1; l <= m; ++l) s->last_res[l - 1] = bits_to_double(hrec[l]);
-  s->predicted = m;
   ++s->steps_done;
+}
+
+// Iterations the next batch is built for.  A batch built for more iterations
+// than a step needs costs little (the surplus launches return at once), one
+// built for fewer loses the rest of the batch; so the prediction follows the
+// largest count of the last batch up at once and down only after two batches
+// in a row stayed below it.
+void update_prediction(mb4_state* s, int batch_max) {
+  if (batch_max >= s->predicted) {
+    s->predicted = batch_max;
+    s->lower_batches = 0;
+  } else if (++s->lower_batches >= 2) {
+    s->predicted = batch_max;
+    s->lower_batches = 0;
+  }
 }
 
 // Fast path: `count` <= kBatch steps enqueued back to back, each with
@@ -499,6 +527,7 @@ int run_batch(mb4_state* s, int count, int iters, int* accepted) {
     accept(s, hrec, mk);
   }
   *accepted = k;
+  if (k > 0) update_prediction(s, *std::max_element(m.begin(), m.begin() + k));
   return prof_collect(s, m);
 }
 
@@ -520,6 +549,7 @@ int step_single(mb4_state* s) {
     const int m = converged_iteration(s, s->h_ring, upto);
     if (m > 0) {
       accept(s, s->h_ring, m);
+      update_prediction(s, m);
       return prof_collect(s, std::vector<int>{m});
     }
     if (m < 0) {
@@ -532,7 +562,7 @@ int step_single(mb4_state* s) {
       return fail(MB4_ENOCONV,
                   "no convergence in %d Newton iterations (||r||_inf = %.3e, tol %.3e)",
                   s->max_newton, bits_to_double(s->h_ring[upto]),
-                  conv_tol(s->eps, bits_to_double(s->h_ring[0])));
+                  conv_tol(s, s->h_ring[0]));
     }
     done = upto;
     batch = 2;
@@ -587,6 +617,8 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     if (opt->inner_sweeps > 0) o.inner_sweeps = opt->inner_sweeps;
     o.stream = opt->stream;
     o.mem_budget = opt->mem_budget;
+    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS)) != 0)
+      return fail(MB4_EINVAL, "unknown bits in flags");
     o.flags = opt->flags;
   }
   if (!all_finite(potential, size_t(sites)))
@@ -611,6 +643,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   s->stream = static_cast<hipStream_t>(o.stream);
   s->q = s->stream;
   s->use_graphs = (o.flags & MB4_FLAG_NO_GRAPHS) == 0;
+  s->relative_eps = (o.flags & MB4_FLAG_RELATIVE_EPS) != 0;
 
   int rc = MB4_OK;
   hipError_t e = hipGetDevice(&s->device);
@@ -681,6 +714,7 @@ int mb4_set_state(mb4_state* s, const double* p, const double* q) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->steps_done = 0;
   s->predicted = kInitialPrediction;
+  s->lower_batches = 0;
   return MB4_OK;
 }
 
@@ -709,6 +743,7 @@ int mb4_set_state_device(mb4_state* s, const double* d_p, const double* d_q) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->steps_done = 0;
   s->predicted = kInitialPrediction;
+  s->lower_batches = 0;
   return MB4_OK;
 }
 
@@ -834,7 +869,7 @@ int mb4_newton_update(mb4_state* s, double* d_U, const double* d_rbar, double* d
   const bool has_r = d_rbar != nullptr;
   const CPlanes3 uin = cplanes_of(d_U, s->sites);
   const CPlanes3 rin = has_r ? cplanes_of(d_rbar, s->sites) : CPlanes3{{nullptr, nullptr, nullptr}};
-  const ConvCheck none{nullptr, 0, 0.0};
+  const ConvCheck none{nullptr, 0, 0.0, false};
   HIP_TRY(mb4::launch_clear(s->dbg_rec, 2, s->stream));
   HIP_TRY(mb4::launch_update_residual(lattice_of(s), uin, P(s->Ua), rin, has_r, false,
                                       planes_of(d_phibar, s->sites), s->dbg_rec + 1, none, none,
@@ -865,7 +900,7 @@ int mb4_stage_solve(mb4_state* s, const double* d_phibar, double* d_rbar, int32_
   const Lattice L = lattice_of(s);
   const CPlanes3 ph = cplanes_of(d_phibar, s->sites);
   const Planes3 ext = planes_of(d_rbar, s->sites);
-  const ConvCheck none{nullptr, 0, 0.0};
+  const ConvCheck none{nullptr, 0, 0.0, false};
   const int fused = std::min(int(sweeps), mb4::kMaxFusedSweeps);
   // Same kernels as a Newton iteration; the last pass writes the caller's
   // planes.

@@ -115,7 +115,8 @@ def test_create_rejects_invalid_arguments(lib, kwargs):
 
 @pytest.mark.parametrize("field,value", [("eps", -1.0), ("eps", float("nan")), ("eps", 1.0),
                                          ("max_newton", -1), ("max_newton", 1001),
-                                         ("inner_sweeps", -2), ("inner_sweeps", 65)])
+                                         ("inner_sweeps", -2), ("inner_sweeps", 65),
+                                         ("flags", 4), ("flags", 0x80000000)])
 def test_create_rejects_invalid_options(lib, field, value):
     opt = M.mb4_options_default()
     setattr(opt, field, value)

@@ -25,11 +25,11 @@ def _golden(name):
     return g
 
 
-def _gpu_run(name, steps, eps, energy_every=0):
+def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False):
     cfg = L.CONFIGS[name]
     v, p, q = L.make_inputs(cfg)
     energies = []
-    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=eps) as st:
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=eps, relative_eps=relative_eps) as st:
         st.set_state(p, q)
         energies.append((0, st.energy()))
         done = 0
@@ -47,7 +47,8 @@ def test_workload_matches_stored_oracle_run(name):
     torch_cuda()
     g = _golden(name)
     every = g["energies"][1][0] if len(g["energies"]) > 1 else 0
-    psi, energies = _gpu_run(name, g["steps"], g["eps"], energy_every=every)
+    psi, energies = _gpu_run(name, g["steps"], g["eps"], energy_every=every,
+                             relative_eps=g["eps_relative"])
     sites = np.array(g["sites"])
     err = np.max(np.abs(psi[sites] - (g["p"] + 1j * g["q"])))
     scale = np.max(np.abs(g["p"] + 1j * g["q"]))

@@ -38,6 +38,23 @@ def test_lattice32_steps_match_oracle(steps):
     assert stats["newton_iters"] >= 2
 
 
+def test_relative_tolerance_matches_oracle():
+    # MB4_FLAG_RELATIVE_EPS: the stopping bound is eps * ||u_0||_inf.  The
+    # GPU takes the oracle's iteration count on the last step and its state.
+    torch_cuda()
+    cfg = L.CONFIGS["lattice32"]
+    v, p, q = L.make_inputs(cfg)
+    orc = O.oracle_for(cfg, v, eps=1e-13, relative=True)
+    ref, _ = orc.run(p + 1j * q, 10)
+    gpu, _, _, stats = _run_gpu(cfg, 10, v, p, q, eps=1e-13, relative_eps=True)
+    assert np.max(np.abs(gpu - ref)) <= 1e-13
+    assert stats["newton_iters"] == orc.iteration_log[-1]
+    absolute = O.oracle_for(cfg, v, eps=1e-13)
+    absolute.run(p + 1j * q, 10)
+    _, _, _, stats_abs = _run_gpu(cfg, 10, v, p, q, eps=1e-13)
+    assert stats_abs["newton_iters"] == absolute.iteration_log[-1]
+
+
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 130), (67, 3), (33, 17), (100, 65)])
 def test_ragged_and_tiny_lattices_match_oracle(nx, ny):
     torch_cuda()

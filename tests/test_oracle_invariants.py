@@ -298,3 +298,33 @@ def test_planted_oracle_mistakes_fail_the_bruteforce_pin(mutation):
         assert err < 5e-15
     else:
         assert err > 1e-12
+
+
+def test_stopping_rule_absolute_and_relative():
+    # Algorithm 1 stops once ||r^l||_inf <= eps (absolute).  For g = 0 the
+    # step is linear in u_0, so scaling u_0 by 2^-50 scales every Newton
+    # update exactly: the relative rule then takes the same iterations and
+    # returns exactly the scaled result, while the absolute rule stops
+    # earlier on the small state.
+    rng = np.random.default_rng(77)
+    nx = ny = 8
+    v = rng.uniform(-1, 1, nx * ny)
+    u0 = (rng.standard_normal(nx * ny) + 1j * rng.standard_normal(nx * ny)) * 0.5
+    scale = 2.0 ** -50
+    lat = O.LatticeNLS(nx, ny, v, 0.0)
+    rel = O.MB4Oracle(lat, 0.05, eps=1e-13, relative=True)
+    a = rel.step(u0)
+    ia = rel.last_iterations
+    b = rel.step(scale * u0)
+    assert rel.last_iterations == ia
+    assert np.array_equal(b, scale * a)
+    ab = O.MB4Oracle(lat, 0.05, eps=1e-13)
+    c = ab.step(u0)
+    ic = ab.last_iterations
+    ab.step(scale * u0)
+    assert ab.last_iterations < ic
+    # The absolute rule at eps equals the relative rule at eps / ||u_0||_inf
+    # up to the rounding of that quotient.
+    m = max(np.max(np.abs(u0.real)), np.max(np.abs(u0.imag)))
+    rel2 = O.MB4Oracle(lat, 0.05, eps=1e-13 / m, relative=True)
+    assert np.array_equal(rel2.step(u0), c) and rel2.last_iterations == ic
