@@ -556,19 +556,47 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
   double2 u0v[PER];
   double2 Un[PER][3];
   double vv[PER];
-  // Phase 1: U^iter and W_i on the whole region.
+  // Phase 1: U^iter and W_i on the whole region.  Every load of both
+  // positions is issued before the first store, so that their latencies
+  // overlap (the compiler cannot move loads across the stores of U^iter).
+  double2 ldu[PER][3], ldr[PER][3];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
     const int site = wrap(oy + ly, ny) * nx + wrap(ox + lx, nx);
     gsite[j] = site;
-    double2 W[3];
-    unsigned long long rm_unused;
-    site_update<FROM_U0, true>(L, Uin, rb, site, u0v[j], Un[j], W, rm_unused);
+    u0v[j] = L.u0[site];
     vv[j] = L.V[site];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) sb[i][idx] = W[i];
+    for (int i = 0; i < 3; ++i) {
+      ldr[j][i] = rb.s[i][site];
+      if (!FROM_U0) ldu[j][i] = Uin.s[i][site];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kIterThreads;
+    const int lx = idx % RX, ly = idx / RX;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double2 base = FROM_U0 ? u0v[j] : ldu[j][i];
+      const double2 d = t_apply(i, ldr[j]);
+      Un[j][i] = make_double2(base.x + d.x, base.y + d.y);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sb[i][idx] = make_double2(MB4_E0[i] * u0v[j].x + MB4_E[i][0] * Un[j][0].x +
+                                    MB4_E[i][1] * Un[j][1].x + MB4_E[i][2] * Un[j][2].x,
+                                MB4_E0[i] * u0v[j].y + MB4_E[i][0] * Un[j][0].y +
+                                    MB4_E[i][1] * Un[j][1].y + MB4_E[i][2] * Un[j][2].y);
+    }
+    // U^iter of the tile goes out now, while it is in registers.
+    if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY && ox + lx < nx &&
+        oy + ly < ny) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Uout.s[i][gsite[j]] = Un[j][i];
+    }
   }
   __syncthreads();
 
@@ -681,7 +709,7 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
     }
   }
   __syncthreads();
-  // The tile: U^iter and rbar^{iter+1} back to HBM, and the update norm.
+  // The tile: rbar^{iter+1} back to HBM, and the update norm.
   unsigned long long rm = 0ull;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
@@ -690,20 +718,11 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
     if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY && ox + lx < nx &&
         oy + ly < ny) {
       const int site = gsite[j];
-      double2 r[3], rp[3];
+      double2 r[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         r[i] = sb[i][idx];
         rout.s[i][site] = r[i];
-        rp[i] = rb.s[i][site];
-      }
-      // U^iter again from its inputs (cheaper than keeping it live in
-      // registers across the sweeps).
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double2 base = FROM_U0 ? L.u0[site] : Uin.s[i][site];
-        const double2 d = t_apply(i, rp);
-        Uout.s[i][site] = make_double2(base.x + d.x, base.y + d.y);
       }
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
