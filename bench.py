@@ -228,7 +228,9 @@ def main(argv=None) -> int:
         "config": {"workload": cfg.name, "nx": cfg.nx, "ny": cfg.ny, "h": cfg.h, "g": cfg.g,
                    "disorder_w": cfg.disorder_w, "defects": cfg.defect_count,
                    "defect_v": cfg.defect_v, "sigma": cfg.sigma, "seed": cfg.seed,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "newton_eps": args.eps or 1e-13, "newton_test": "absolute (Algorithm 1)",
+                   "inner_sweeps": stats["inner_sweeps"] // max(stats["newton_iters"], 1)},
         "energy_drift": drift,
         "energy_drift_ok": drift <= 1e-14,
         "newton_iters_last": stats["newton_iters"],

@@ -56,6 +56,28 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * q + min(x, r) + k;
 }
 
+// Tile (tx, ty) of block b (after xcd_block) on a tiles_x x tiles_y grid,
+// walked in vertical strips kStrip tiles wide, row by row inside a strip.
+// The blocks in flight on one XCD then hold vertically as well as
+// horizontally adjacent tiles, so the halo rows a tile shares with the one
+// above are still in that XCD's L2 (a row-major walk over a wide lattice
+// has moved on by a whole tile row before they are read again).
+constexpr int kStrip = 16;
+__device__ __forceinline__ void strip_tile(int b, int tiles_x, int tiles_y, int& tx, int& ty) {
+  const int full = tiles_x / kStrip;
+  const int per = kStrip * tiles_y;
+  if (b < full * per) {
+    const int r = b % per;
+    tx = (b / per) * kStrip + r % kStrip;
+    ty = r / kStrip;
+  } else {
+    const int w = tiles_x - full * kStrip;
+    const int r = b - full * per;
+    tx = full * kStrip + r % w;
+    ty = r / w;
+  }
+}
+
 __device__ __forceinline__ unsigned long long abs_bits(double v) {
   // |v| as an ordered bit pattern; NaN patterns sort above +inf, so a NaN
   // survives an unsigned max and later fails every convergence test.
@@ -359,9 +381,11 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
   __shared__ double2 sr[3][RN];
   __shared__ double2 su[UN];
   const int nx = L.nx, ny = L.ny;
-  const int tiles_x = (nx + TSX - 1) / TSX;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int tx0 = (b % tiles_x) * TSX, ty0 = (b / tiles_x) * TSY;
+  int tx0, ty0;
+  strip_tile(xcd_block(blockIdx.x, gridDim.x), (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0,
+             ty0);
+  tx0 *= TSX;
+  ty0 *= TSY;
 
   // Own positions first: their potential is loaded before the u_0 staging
   // below, so both sets of loads are in flight together.
@@ -526,9 +550,11 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
   constexpr int TSX = iter_tile_x(H), TSY = iter_tile_y(H);
   constexpr int PER = RN / kIterThreads;
   const int nx = L.nx, ny = L.ny;
-  const int tiles_x = (nx + TSX - 1) / TSX;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int tx0 = (b % tiles_x) * TSX, ty0 = (b / tiles_x) * TSY;
+  int tx0, ty0;
+  strip_tile(xcd_block(blockIdx.x, gridDim.x), (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0,
+             ty0);
+  tx0 *= TSX;
+  ty0 *= TSY;
   const int ox = tx0 - H - 1, oy = ty0 - H - 1;  // region origin
 
   if (converged_at(fin)) {
