@@ -200,6 +200,85 @@ MB4_API int mb4_newton_update(mb4_state* state, double* d_U, const double* d_rba
 MB4_API int mb4_stage_solve(mb4_state* state, const double* d_phibar, double* d_rbar,
                     int32_t sweeps);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent lattice problems (disorder realisations, say)
+ * advanced together.  Every Newton phase of every member runs in one launch
+ * over all members' tiles, with the same kernels and arithmetic as a single
+ * state, so a member's trajectory is bit for bit the one mb4_step gives for
+ * it alone.  Steps are replayed from HIP graphs as for a single state.  Each
+ * member converges and is accepted on its own (Algorithm 1 per member);
+ * members that need more Newton iterations do not hold the others back
+ * beyond the batch in which it happens.
+ *
+ * Member fields are stored one after the other: 216 bytes per site
+ * (potential, u_0, two stage-value fields, two stage-correction fields) plus
+ * the step records (8 * 32 * (max_newton + 1) bytes per member). */
+typedef struct mb4_ensemble mb4_ensemble;
+
+/* Shapes of the solve regions (positions per block; the output tile is the
+ * region less the halo the sweeps need).  All give identical results; the
+ * speed depends on the lattice sizes, which mb4_ensemble_tune measures. */
+#define MB4_REGION_32x32 0
+#define MB4_REGION_64x16 1
+#define MB4_REGION_32x16 2
+#define MB4_REGION_COUNT 3
+
+/* Creates an ensemble of `count` (1 .. 65536) members on the current device.
+ *  lattices, nonlinearities, h: host arrays of `count` entries, each as for
+ *    mb4_create (h finite and non-zero).
+ *  potentials: host array of `count` pointers, member m's to nx*ny finite
+ *    doubles (copied).
+ *  opt: as for mb4_create, except that inner_sweeps must be at most 4 (one
+ *    temporally blocked pass per stage solve); NULL for the defaults.
+ * Members start at psi = 0.  Region MB4_REGION_32x32 until set or tuned.
+ * Errors: MB4_EINVAL (before any device work), MB4_ENOMEM, MB4_EDEVICE. */
+MB4_API int mb4_ensemble_create(int32_t count, const mb4_lattice* lattices,
+                                const double* const* potentials,
+                                const mb4_nonlinearity* nonlinearities, const double* h,
+                                const mb4_options* opt, mb4_ensemble** out);
+
+/* Frees the ensemble's device memory.  NULL-safe. */
+MB4_API void mb4_ensemble_destroy(mb4_ensemble* ens);
+
+/* Number of members; -1 for NULL. */
+MB4_API int32_t mb4_ensemble_size(const mb4_ensemble* ens);
+
+/* psi of member m from / to host arrays of its nx*ny doubles; setting resets
+ * the member's step counter.  Errors: MB4_EINVAL (bad member, NULL, or
+ * non-finite input), MB4_EDEVICE. */
+MB4_API int mb4_ensemble_set_state(mb4_ensemble* ens, int32_t member, const double* p,
+                                   const double* q);
+MB4_API int mb4_ensemble_get_state(mb4_ensemble* ens, int32_t member, double* p, double* q);
+
+/* Advances every member by nsteps >= 0 steps.  Steps are all-or-nothing per
+ * member.  If a member's Newton loop fails (max_newton iterations or a
+ * non-finite update), the call returns MB4_ENOCONV; that member keeps its
+ * last accepted step, others may be further on, and
+ * mb4_ensemble_member_stats tells where each one is. */
+MB4_API int mb4_ensemble_step(mb4_ensemble* ens, int64_t nsteps);
+
+/* out[6 m + k] = the six components of mb4_energy_components for member m;
+ * out holds 6 * count doubles. */
+MB4_API int mb4_ensemble_energy_components(mb4_ensemble* ens, double* out);
+
+/* Steps accepted by member m since its last set_state, and the Newton
+ * iterations of its last accepted step.  Either pointer may be NULL. */
+MB4_API int mb4_ensemble_member_stats(const mb4_ensemble* ens, int32_t member,
+                                      int64_t* steps_done, int32_t* newton_iters);
+
+/* Selects the solve-region shape (MB4_REGION_*). */
+MB4_API int mb4_ensemble_set_region(mb4_ensemble* ens, int32_t region);
+MB4_API int32_t mb4_ensemble_region(const mb4_ensemble* ens);
+
+/* Autotuner: times `steps` (>= 1) steps of the ensemble with each region
+ * shape whose tiles are non-empty, keeps the fastest, and restores every
+ * member's state and counters, so the run continues as if it had not been
+ * called.  ms_per_step (may be NULL) receives MB4_REGION_COUNT times in ms
+ * per step (negative for a shape not tried); *best (may be NULL) the shape
+ * kept.  Uses 16 bytes per site of temporary device memory. */
+MB4_API int mb4_ensemble_tune(mb4_ensemble* ens, int32_t steps, int32_t* best,
+                              double* ms_per_step);
+
 /* Static description of a status code. */
 MB4_API const char* mb4_strerror(int code);
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmb4.so")
-SOURCES = ["mb4_kernels.hip", "mb4_runtime.hip"]
+SOURCES = ["mb4_kernels.hip", "mb4_runtime.hip", "mb4_ensemble.hip"]
 ARCH = "gfx950"
 
 

@@ -44,6 +44,39 @@ struct ConvCheck {
   bool relative;                  // ... or <= eps * ||u_0||_inf (rec[0])
 };
 
+// Several independent lattices ("members") advanced by the same launches.
+// Member m's sites are [base, base + nx*ny) of ensemble-wide fields, whose
+// planes are all members' sites long; its step record starts rec_stride words
+// after member m-1's.  A block finds its member by binary search in block0.
+struct MemberDesc {
+  int nx, ny;
+  double t, shift, g, h;
+  long long base;
+};
+
+struct Multi {
+  const MemberDesc* desc = nullptr;  // device [count]; NULL: the Lattice argument alone
+  const int* block0 = nullptr;       // device [count + 1]: first block of each member
+  int count = 0;
+  int blocks = 0;                    // blocks of the launch (block0[count])
+  const int* todo = nullptr;         // device [count]: steps of the batch each member takes
+  int step = 0;                      // step of the batch this launch belongs to
+  int rec_stride = 0;                // record words between consecutive members
+};
+
+// Region shapes of the temporally blocked solve kernels (positions per
+// block, two per thread).
+enum Region : int { kRegion32x32 = 0, kRegion64x16 = 1, kRegion32x16 = 2, kRegionCount = 3 };
+const char* region_name(int region);
+
+// Output tile of the first-iteration solve and of the fused iteration for a
+// region and sweeps (1..4); sites per block of the final update and of the
+// energy partial sums.
+void first_solve_tile(int region, int sweeps, int* tx, int* ty);
+void iterate_tile(int region, int sweeps, int* tx, int* ty);
+constexpr int kFinalSites = 256;
+void energy_tile(int* tx, int* ty);
+
 // Optional timestamps of one launch (both NULL: untimed).
 struct LaunchEvents {
   hipEvent_t start = nullptr;
@@ -54,6 +87,11 @@ struct LaunchEvents {
 // p[0 .. n) = 0 (a kernel, so that it may sit in a captured graph).
 hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 
+// The launchers below that take a Multi run every member of it when mu.desc is
+// not NULL: the Lattice then carries ensemble-wide V and u0, planes and
+// records are those of member 0, and `region` picks the solve-region shape.
+// Members with todo[m] <= mu.step do nothing.
+
 // Newton iteration 1, stage solve: `sweeps` (1..4) block-Jacobi sweeps of
 // (I - h lambda_i J) r_i = -Phibar_i with Phibar_i = -h TC_i f(u_0) (the
 // residual at U^0 = e_3 (x) u_0) built in place, into rout.  Records
@@ -61,7 +99,8 @@ hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 // and writes that Phibar to phib_out when phib_out.s[0] is not NULL.
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
-                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {});
+                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {},
+                              const Multi& mu = {}, int region = kRegion32x32);
 
 // Newton iteration l >= 2 (or a kernel-level call), stage solve: `sweeps`
 // (1..4) block-Jacobi sweeps from r = 0 for the three stage systems
@@ -101,13 +140,14 @@ hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout
 hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                           Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
                           ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
-                          LaunchEvents ev = {});
+                          LaunchEvents ev = {}, const Multi& mu = {},
+                          int region = kRegion32x32);
 
 // Update pass of the last iteration of a batch: the final update of u0_out if
 // `fin` holds and `check` does not; nothing otherwise.
 hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
                                ConvCheck check, ConvCheck fin, double2* u0_out,
-                               hipStream_t stream, LaunchEvents ev = {});
+                               hipStream_t stream, LaunchEvents ev = {}, const Multi& mu = {});
 
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,
@@ -120,5 +160,15 @@ hipError_t launch_deinterleave(const double2* in, double* p, double* q, int n,
 size_t energy_partials_count(int nx, int ny);
 hipError_t launch_energy(const Lattice& lat, double* partials, double* out,
                          hipStream_t stream);
+// The same for every member of a Multi (block0 over energy tiles): out[6 m + k];
+// partials holds 12 doubles per block.
+hipError_t launch_energy_multi(const Lattice& lat, const Multi& mu, double* partials,
+                               double* out, hipStream_t stream);
+
+// Host runtime: records `fmt` as the calling thread's error detail (what
+// mb4_error_detail returns) and returns `code`.
+namespace rt {
+int fail(int code, const char* fmt, ...);
+}  // namespace rt
 
 }  // namespace mb4

@@ -103,6 +103,57 @@ __device__ __forceinline__ bool converged_at(const ConvCheck& c) {
   return r <= (c.relative ? conv_tol(c.eps, bits_double(c.rec[0])) : c.eps);
 }
 
+// Where block b (after xcd_block) works: for a Multi, its member's lattice
+// replaces L (with V and u0 moved to the member's sites), b becomes the block
+// index within the member, and `base` / `rec` are the member's site and
+// record offsets.  `skip`: the member takes no more steps in this batch.
+struct Loc {
+  int b;
+  long long base, rec;
+  bool skip;
+};
+
+__device__ __forceinline__ Loc locate(const Multi& mu, Lattice& L, int b) {
+  Loc w{b, 0, 0, false};
+  if (mu.desc == nullptr) return w;
+  int lo = 0, hi = mu.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mu.block0[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const MemberDesc d = mu.desc[lo];
+  w.b = b - mu.block0[lo];
+  w.base = d.base;
+  w.rec = static_cast<long long>(lo) * mu.rec_stride;
+  w.skip = mu.todo != nullptr && mu.step >= mu.todo[lo];
+  L.nx = d.nx;
+  L.ny = d.ny;
+  L.t = d.t;
+  L.shift = d.shift;
+  L.g = d.g;
+  L.h = d.h;
+  L.V += d.base;
+  L.u0 += d.base;
+  return w;
+}
+
+template <class P>
+__device__ __forceinline__ void offset_planes(P& p, long long base) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (p.s[i] != nullptr) p.s[i] += base;
+}
+
+__device__ __forceinline__ void offset_check(ConvCheck& c, long long rec) {
+  if (c.rec != nullptr) c.rec += rec;
+}
+
+template <class T>
+__device__ __forceinline__ T* offset_ptr(T* p, long long n) {
+  return p == nullptr ? p : p + n;
+}
+
 // Block-wide max of v posted to *slot.  Device-scope atomics on one address
 // serialise across the XCDs; most blocks hold a value below the running
 // maximum, so thread 0 reads it first (a coherent load) and only posts a
@@ -132,9 +183,8 @@ struct TileCoord {
   bool inside;
 };
 
-__device__ __forceinline__ TileCoord tile_coord(int nx, int ny) {
+__device__ __forceinline__ TileCoord tile_coord_at(int nx, int ny, int b) {
   const int tiles_x = (nx + kTX - 1) / kTX;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
   TileCoord c;
   c.x0 = (b % tiles_x) * kTX;
   c.y0 = (b / tiles_x) * kTY;
@@ -142,6 +192,10 @@ __device__ __forceinline__ TileCoord tile_coord(int nx, int ny) {
   c.y = c.y0 + (threadIdx.x / kTX);
   c.inside = c.x < nx && c.y < ny;
   return c;
+}
+
+__device__ __forceinline__ TileCoord tile_coord(int nx, int ny) {
+  return tile_coord_at(nx, ny, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // r = (T (x) I) rbar at one site, component of stage j.
@@ -349,32 +403,44 @@ __device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v,
 // shrinking by one ring per sweep, and only the tile's interior goes back to
 // HBM.  Each region position computes the iterate of its (wrapped) lattice
 // site from its own region neighbours, so lattices smaller than the region
-// give the same values as large ones.  The region is always 32 x 32 = 1024
-// positions, two per thread, so the tile shrinks as the halo grows.
+// give the same values as large ones.  The region is RX x RY positions (32 x 32
+// by default; Region lists the shapes built), two per thread, so the tile
+// shrinks as the halo grows.
 //
 // FIRST: Newton iteration 1.  The right-hand side -Phibar_i = h TC_i f(u_0)
 // is built in place (TC = T^-1 c) from u_0 staged in LDS on the region plus
 // a one-site ring; ||u_0||_inf goes to *u0max_slot; with store_rhs the tile's
 // Phibar is also written out (for extra plain sweeps).
-constexpr int kRX = 32;
-constexpr int kRY = 32;
-constexpr int kSolveThreads = 512;
-__host__ __device__ constexpr int solve_tile_x(int h) { return kRX - 2 * h; }
-__host__ __device__ constexpr int solve_tile_y(int h) { return kRY - 2 * h; }
+__host__ __device__ constexpr int region_x(int region) {
+  return region == kRegion64x16 ? 64 : 32;
+}
+__host__ __device__ constexpr int region_y(int region) {
+  return region == kRegion32x32 ? 32 : 16;
+}
 
 struct FirstArgs {
   unsigned long long* u0max_slot;  // ||u_0||_inf target
   bool store_rhs;                  // also write Phibar of the tile
 };
 
-template <int H, bool FIRST>
-__global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
-                                                                 Planes3 phib_out, Planes3 rout,
-                                                                 unsigned long long* rslot,
-                                                                 ConvCheck chk, FirstArgs fa) {
+template <int RX, int RY, int H, bool FIRST>
+__global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
+                                                              Planes3 phib_out, Planes3 rout,
+                                                              unsigned long long* rslot,
+                                                              ConvCheck chk, FirstArgs fa,
+                                                              Multi mu) {
+  constexpr int kSolveThreads = RX * RY / 2;
+  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
+  if (w.skip) return;
+  offset_check(chk, w.rec);
   if (converged_at(chk)) return;
-  constexpr int RX = kRX, RY = kRY, RN = RX * RY;
-  constexpr int TSX = solve_tile_x(H), TSY = solve_tile_y(H);
+  offset_planes(phib_in, w.base);
+  offset_planes(phib_out, w.base);
+  offset_planes(rout, w.base);
+  rslot = offset_ptr(rslot, w.rec);
+  fa.u0max_slot = offset_ptr(fa.u0max_slot, w.rec);
+  constexpr int RN = RX * RY;
+  constexpr int TSX = RX - 2 * H, TSY = RY - 2 * H;
   constexpr int PER = RN / kSolveThreads;
   static_assert(RN % kSolveThreads == 0, "region must be a whole number of passes");
   constexpr int UX = RX + 2, UN = FIRST ? UX * (RY + 2) : 1;
@@ -382,8 +448,7 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
   __shared__ double2 su[UN];
   const int nx = L.nx, ny = L.ny;
   int tx0, ty0;
-  strip_tile(xcd_block(blockIdx.x, gridDim.x), (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0,
-             ty0);
+  strip_tile(w.b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
   tx0 *= TSX;
   ty0 *= TSY;
 
@@ -526,33 +591,37 @@ __global__ __launch_bounds__(kSolveThreads, 4) void k_stage_solve(Lattice L, CPl
 //   rec[iter + 1] = ||(T (x) I) rbar^{iter+1}||_inf
 // unless iteration iter already met the tolerance, in which case the block
 // writes u_1 = U_3^{iter-1} + (T rbar^iter)_3 over u_0 for its tile (Sec. 2.2:
-// c_3 = 1) and stops.  A 512-thread block works on a 32 x 32 region, two
-// positions per thread: W_i (Eq. fKu2) on the whole region in LDS, the
-// residual on the region less one ring, the sweeps on shrinking rings, and
-// the (30 - 2H) x (30 - 2H) tile in the middle is written back.  As in
+// c_3 = 1) and stops.  A block works on an RX x RY region (32 x 32 with 512
+// threads by default), two positions per thread: W_i (Eq. fKu2) on the whole
+// region in LDS, the residual on the region less one ring, the sweeps on
+// shrinking rings, and the (RX - 2 - 2H) x (RY - 2 - 2H) tile in the middle
+// is written back.  As in
 // k_stage_solve, each region position computes the values of its (wrapped)
 // lattice site from region neighbours only.
-constexpr int kIX = 32;
-constexpr int kIY = 32;
-constexpr int kIterThreads = 512;
-__host__ __device__ constexpr int iter_tile_x(int h) { return kIX - 2 - 2 * h; }
-__host__ __device__ constexpr int iter_tile_y(int h) { return kIY - 2 - 2 * h; }
-
-template <bool FROM_U0, int H>
-__global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(Lattice L, CPlanes3 Uin,
-                                                             Planes3 Uout, CPlanes3 rb,
-                                                             Planes3 rout,
-                                                             unsigned long long* rnext,
-                                                             ConvCheck chk, ConvCheck fin,
-                                                             double2* u0_out) {
+template <int RX, int RY, bool FROM_U0, int H>
+__global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 Uin, Planes3 Uout,
+                                                          CPlanes3 rb, Planes3 rout,
+                                                          unsigned long long* rnext,
+                                                          ConvCheck chk, ConvCheck fin,
+                                                          double2* u0_out, Multi mu) {
+  constexpr int kIterThreads = RX * RY / 2;
+  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
+  if (w.skip) return;
+  offset_check(chk, w.rec);
   if (converged_at(chk)) return;
-  constexpr int RX = kIX, RY = kIY, RN = RX * RY;
-  constexpr int TSX = iter_tile_x(H), TSY = iter_tile_y(H);
+  offset_check(fin, w.rec);
+  offset_planes(Uin, w.base);
+  offset_planes(Uout, w.base);
+  offset_planes(rb, w.base);
+  offset_planes(rout, w.base);
+  rnext = offset_ptr(rnext, w.rec);
+  u0_out = offset_ptr(u0_out, w.base);
+  constexpr int RN = RX * RY;
+  constexpr int TSX = RX - 2 - 2 * H, TSY = RY - 2 - 2 * H;
   constexpr int PER = RN / kIterThreads;
   const int nx = L.nx, ny = L.ny;
   int tx0, ty0;
-  strip_tile(xcd_block(blockIdx.x, gridDim.x), (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0,
-             ty0);
+  strip_tile(w.b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
   tx0 *= TSX;
   ty0 *= TSY;
   const int ox = tx0 - H - 1, oy = ty0 - H - 1;  // region origin
@@ -764,11 +833,19 @@ __global__ __launch_bounds__(kIterThreads, 2048 / kIterThreads) void k_iterate(L
 // update u_1 = U_3 + (T rbar)_3 (base U_3 = Uin[2], or u_0 if from_u0) if that
 // iteration met the tolerance and none before it did; nothing otherwise.
 template <bool FROM_U0>
-__global__ __launch_bounds__(256) void k_final_update(Lattice L, CPlanes3 Uin, CPlanes3 rb,
-                                                      ConvCheck chk, ConvCheck fin,
-                                                      double2* u0_out, int n) {
+__global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes3 Uin, CPlanes3 rb,
+                                                              ConvCheck chk, ConvCheck fin,
+                                                              double2* u0_out, int n, Multi mu) {
+  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
+  if (w.skip) return;
+  offset_check(chk, w.rec);
+  offset_check(fin, w.rec);
   if (converged_at(chk) || !converged_at(fin)) return;
-  const int site = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (mu.desc != nullptr) n = L.nx * L.ny;
+  offset_planes(Uin, w.base);
+  offset_planes(rb, w.base);
+  u0_out = offset_ptr(u0_out, w.base);
+  const int site = w.b * kFinalSites + threadIdx.x;
   if (site >= n) return;
   double2 r[3];
 #pragma unroll
@@ -834,11 +911,15 @@ __device__ __forceinline__ DD dd_add(DD a, DD b) {
 
 constexpr int kEnergyParts = 6;
 
-// Per-block sums of the six energy terms; partials[(block*6 + k)*2 + {0,1}].
-__global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* partials) {
+// Per-block sums of the six energy terms; partials[(block*6 + k)*2 + {0,1}]
+// with block the XCD-remapped index, so that a member's blocks are
+// contiguous.
+__global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* partials, Multi mu) {
   __shared__ DD red[kEnergyParts][kTile];
+  const int bl = xcd_block(blockIdx.x, gridDim.x);
+  const Loc w = locate(mu, L, bl);
   const int nx = L.nx, ny = L.ny;
-  const TileCoord c = tile_coord(nx, ny);
+  const TileCoord c = tile_coord_at(nx, ny, w.b);
   double v[kEnergyParts] = {0, 0, 0, 0, 0, 0};
   if (c.inside) {
     const int site = c.y * nx + c.x;
@@ -873,18 +954,26 @@ __global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* par
   }
   if (threadIdx.x < kEnergyParts) {
     const DD s = red[threadIdx.x][0];
-    partials[(static_cast<size_t>(blockIdx.x) * kEnergyParts + threadIdx.x) * 2 + 0] = s.hi;
-    partials[(static_cast<size_t>(blockIdx.x) * kEnergyParts + threadIdx.x) * 2 + 1] = s.lo;
+    partials[(static_cast<size_t>(bl) * kEnergyParts + threadIdx.x) * 2 + 0] = s.hi;
+    partials[(static_cast<size_t>(bl) * kEnergyParts + threadIdx.x) * 2 + 1] = s.lo;
   }
 }
 
+// Sum of the partials of blocks [first, last) into out[0 .. 6), in a fixed
+// order.  One block per output: block m of a Multi sums member m's blocks.
 __global__ __launch_bounds__(kTile) void k_energy_final(const double* partials, int nblocks,
-                                                         double* out) {
+                                                         const int* block0, double* out) {
   __shared__ DD red[kEnergyParts][kTile];
+  int first = 0, last = nblocks;
+  if (block0 != nullptr) {
+    first = block0[blockIdx.x];
+    last = block0[blockIdx.x + 1];
+    out += kEnergyParts * blockIdx.x;
+  }
   DD acc[kEnergyParts];
 #pragma unroll
   for (int k = 0; k < kEnergyParts; ++k) acc[k] = DD{0.0, 0.0};
-  for (int bkt = threadIdx.x; bkt < nblocks; bkt += kTile) {
+  for (int bkt = first + threadIdx.x; bkt < last; bkt += kTile) {
 #pragma unroll
     for (int k = 0; k < kEnergyParts; ++k) {
       const size_t o = (static_cast<size_t>(bkt) * kEnergyParts + k) * 2;
@@ -923,11 +1012,6 @@ __global__ __launch_bounds__(256) void k_deinterleave(const double2* in, double*
 
 int tile_blocks(int nx, int ny) {
   return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
-}
-
-int solve_blocks(int nx, int ny, int h) {
-  const int tx = solve_tile_x(h), ty = solve_tile_y(h);
-  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
 }
 
 }  // namespace
@@ -971,50 +1055,114 @@ hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout
                rslot, check, fin, u0_out);
 }
 
-hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, int sweeps,
-                              unsigned long long* rslot, ConvCheck check, hipStream_t stream,
-                              LaunchEvents ev) {
-  const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
-  const Planes3 none{{nullptr, nullptr, nullptr}};
-  const FirstArgs fa{nullptr, false};
+const char* region_name(int region) {
+  switch (region) {
+    case kRegion32x32: return "32x32";
+    case kRegion64x16: return "64x16";
+    case kRegion32x16: return "32x16";
+    default: return "?";
+  }
+}
+
+void first_solve_tile(int region, int sweeps, int* tx, int* ty) {
+  *tx = region_x(region) - 2 * (sweeps - 1);
+  *ty = region_y(region) - 2 * (sweeps - 1);
+}
+
+void iterate_tile(int region, int sweeps, int* tx, int* ty) {
+  *tx = region_x(region) - 2 - 2 * (sweeps - 1);
+  *ty = region_y(region) - 2 - 2 * (sweeps - 1);
+}
+
+void energy_tile(int* tx, int* ty) {
+  *tx = kTX;
+  *ty = kTY;
+}
+
+namespace {
+
+template <int RX, int RY, bool FIRST>
+hipError_t launch_solve_region(const Lattice& lat, CPlanes3 phib_in, Planes3 phib_out,
+                               Planes3 rout, unsigned long long* rslot, ConvCheck check,
+                               FirstArgs fa, int sweeps, const Multi& mu, hipStream_t stream,
+                               LaunchEvents ev) {
+  const int h = sweeps - 1, tx = RX - 2 * h, ty = RY - 2 * h;
+  const dim3 grid(mu.desc != nullptr ? mu.blocks
+                                     : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
+      block(RX * RY / 2);
   switch (sweeps) {
     case 1:
-      MB4_LAUNCH((k_stage_solve<0, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
-                 fa);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 0, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+                 rslot, check, fa, mu);
     case 2:
-      MB4_LAUNCH((k_stage_solve<1, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
-                 fa);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 1, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+                 rslot, check, fa, mu);
     case 3:
-      MB4_LAUNCH((k_stage_solve<2, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
-                 fa);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 2, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+                 rslot, check, fa, mu);
     case 4:
-      MB4_LAUNCH((k_stage_solve<3, false>), grid, block, ev, lat, phib, none, rout, rslot, check,
-                 fa);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 3, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+                 rslot, check, fa, mu);
     default:
       return hipErrorInvalidValue;
   }
 }
 
+template <int RX, int RY, bool F>
+hipError_t launch_iterate_region(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
+                                 Planes3 rout, int sweeps, unsigned long long* rnext,
+                                 ConvCheck check, ConvCheck fin, double2* u0_out,
+                                 const Multi& mu, hipStream_t stream, LaunchEvents ev) {
+  const int h = sweeps - 1, tx = RX - 2 - 2 * h, ty = RY - 2 - 2 * h;
+  const dim3 grid(mu.desc != nullptr ? mu.blocks
+                                     : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
+      block(RX * RY / 2);
+  switch (sweeps) {
+    case 1:
+      MB4_LAUNCH((k_iterate<RX, RY, F, 0>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+                 check, fin, u0_out, mu);
+    case 2:
+      MB4_LAUNCH((k_iterate<RX, RY, F, 1>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+                 check, fin, u0_out, mu);
+    case 3:
+      MB4_LAUNCH((k_iterate<RX, RY, F, 2>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+                 check, fin, u0_out, mu);
+    case 4:
+      MB4_LAUNCH((k_iterate<RX, RY, F, 3>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+                 check, fin, u0_out, mu);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, int sweeps,
+                              unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                              LaunchEvents ev) {
+  const Planes3 none{{nullptr, nullptr, nullptr}};
+  return launch_solve_region<32, 32, false>(lat, phib, none, rout, rslot, check,
+                                            FirstArgs{nullptr, false}, sweeps, Multi{}, stream,
+                                            ev);
+}
+
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
-                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev) {
-  const dim3 grid(solve_blocks(lat.nx, lat.ny, sweeps - 1)), block(kSolveThreads);
+                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev,
+                              const Multi& mu, int region) {
   const CPlanes3 none{{nullptr, nullptr, nullptr}};
   const FirstArgs fa{u0max_slot, phib_out.s[0] != nullptr};
   const ConvCheck nochk{nullptr, 0, 0.0, false};
-  switch (sweeps) {
-    case 1:
-      MB4_LAUNCH((k_stage_solve<0, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
-                 nochk, fa);
-    case 2:
-      MB4_LAUNCH((k_stage_solve<1, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
-                 nochk, fa);
-    case 3:
-      MB4_LAUNCH((k_stage_solve<2, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
-                 nochk, fa);
-    case 4:
-      MB4_LAUNCH((k_stage_solve<3, true>), grid, block, ev, lat, none, phib_out, rout, rslot,
-                 nochk, fa);
+  switch (region) {
+    case kRegion32x32:
+      return launch_solve_region<32, 32, true>(lat, none, phib_out, rout, rslot, nochk, fa,
+                                               sweeps, mu, stream, ev);
+    case kRegion64x16:
+      return launch_solve_region<64, 16, true>(lat, none, phib_out, rout, rslot, nochk, fa,
+                                               sweeps, mu, stream, ev);
+    case kRegion32x16:
+      return launch_solve_region<32, 16, true>(lat, none, phib_out, rout, rslot, nochk, fa,
+                                               sweeps, mu, stream, ev);
     default:
       return hipErrorInvalidValue;
   }
@@ -1030,41 +1178,34 @@ hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, P
 hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                           Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
                           ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
-                          LaunchEvents ev) {
-  const int h = sweeps - 1;
-  if (h < 0 || h > 3) return hipErrorInvalidValue;
-  const int tx = iter_tile_x(h), ty = iter_tile_y(h);
-  const dim3 grid(((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)), block(kIterThreads);
-#define MB4_ITER_CASE(F, HH)                                                                 \
-  MB4_LAUNCH((k_iterate<F, HH>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext, check, \
-             fin, u0_out)
-  if (from_u0) {
-    switch (h) {
-      case 0: MB4_ITER_CASE(true, 0);
-      case 1: MB4_ITER_CASE(true, 1);
-      case 2: MB4_ITER_CASE(true, 2);
-      default: MB4_ITER_CASE(true, 3);
-    }
-  } else {
-    switch (h) {
-      case 0: MB4_ITER_CASE(false, 0);
-      case 1: MB4_ITER_CASE(false, 1);
-      case 2: MB4_ITER_CASE(false, 2);
-      default: MB4_ITER_CASE(false, 3);
-    }
+                          LaunchEvents ev, const Multi& mu, int region) {
+#define MB4_ITER_REGION(RX, RY)                                                              \
+  return from_u0 ? launch_iterate_region<RX, RY, true>(lat, Uin, Uout, rbar, rout, sweeps,  \
+                                                       rnext, check, fin, u0_out, mu, stream, \
+                                                       ev)                                    \
+                 : launch_iterate_region<RX, RY, false>(lat, Uin, Uout, rbar, rout, sweeps, \
+                                                        rnext, check, fin, u0_out, mu,      \
+                                                        stream, ev)
+  switch (region) {
+    case kRegion32x32: MB4_ITER_REGION(32, 32);
+    case kRegion64x16: MB4_ITER_REGION(64, 16);
+    case kRegion32x16: MB4_ITER_REGION(32, 16);
+    default: return hipErrorInvalidValue;
   }
-#undef MB4_ITER_CASE
+#undef MB4_ITER_REGION
 }
 
 hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
                                ConvCheck check, ConvCheck fin, double2* u0_out,
-                               hipStream_t stream, LaunchEvents ev) {
+                               hipStream_t stream, LaunchEvents ev, const Multi& mu) {
   const int n = lat.nx * lat.ny;
-  const dim3 grid((n + 255) / 256), block(256);
+  const dim3 grid(mu.desc != nullptr ? mu.blocks : (n + kFinalSites - 1) / kFinalSites),
+      block(kFinalSites);
   if (from_u0)
-    MB4_LAUNCH(k_final_update<true>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n);
+    MB4_LAUNCH(k_final_update<true>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n, mu);
   else
-    MB4_LAUNCH(k_final_update<false>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n);
+    MB4_LAUNCH(k_final_update<false>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n,
+               mu);
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,
@@ -1083,12 +1224,23 @@ size_t energy_partials_count(int nx, int ny) {
 
 hipError_t launch_energy(const Lattice& lat, double* partials, double* out, hipStream_t stream) {
   const int nb = tile_blocks(lat.nx, lat.ny);
-  hipExtLaunchKernelGGL(k_energy_partial, dim3(nb), dim3(kTile), 0, stream, nullptr, nullptr, 0u,
-                        lat, partials);
+  hipLaunchKernelGGL(k_energy_partial, dim3(nb), dim3(kTile), 0, stream, lat, partials, Multi{});
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipExtLaunchKernelGGL(k_energy_final, dim3(1), dim3(kTile), 0, stream, nullptr, nullptr, 0u,
-                        static_cast<const double*>(partials), nb, out);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kTile), 0, stream,
+                     static_cast<const double*>(partials), nb, static_cast<const int*>(nullptr),
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_multi(const Lattice& lat, const Multi& mu, double* partials,
+                               double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_energy_partial, dim3(mu.blocks), dim3(kTile), 0, stream, lat, partials,
+                     mu);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_energy_final, dim3(mu.count), dim3(kTile), 0, stream,
+                     static_cast<const double*>(partials), mu.blocks, mu.block0, out);
   return hipGetLastError();
 }
 

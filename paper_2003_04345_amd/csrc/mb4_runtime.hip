@@ -44,15 +44,7 @@ constexpr int kBatch = 32;  // steps enqueued per host round trip
 
 thread_local std::string g_detail;
 
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_detail = buf;
-  return code;
-}
+using mb4::rt::fail;
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
@@ -575,6 +567,16 @@ int check_state(const mb4_state* s) {
 }
 
 }  // namespace
+
+int mb4::rt::fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_detail = buf;
+  return code;
+}
 
 extern "C" {
 

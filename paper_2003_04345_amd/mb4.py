@@ -39,6 +39,12 @@ class mb4_options(Structure):
 MB4_FLAG_NO_GRAPHS = 1
 MB4_FLAG_RELATIVE_EPS = 2
 
+MB4_REGION_32x32 = 0
+MB4_REGION_64x16 = 1
+MB4_REGION_32x16 = 2
+MB4_REGION_COUNT = 3
+REGION_NAMES = ("32x32", "64x16", "32x16")
+
 
 class Mb4Error(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
@@ -70,6 +76,19 @@ _SIGNATURES = {
     "mb4_profile_classes": (c_int32, []),
     "mb4_profile_name": (c_char_p, [c_int32]),
     "mb4_profile_read": (c_int, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
+    "mb4_ensemble_create": (c_int, [c_int32, POINTER(mb4_lattice), POINTER(POINTER(c_double)),
+                                    POINTER(mb4_nonlinearity), POINTER(c_double),
+                                    POINTER(mb4_options), POINTER(c_void_p)]),
+    "mb4_ensemble_destroy": (None, [c_void_p]),
+    "mb4_ensemble_size": (c_int32, [c_void_p]),
+    "mb4_ensemble_set_state": (c_int, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
+    "mb4_ensemble_get_state": (c_int, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
+    "mb4_ensemble_step": (c_int, [c_void_p, c_int64]),
+    "mb4_ensemble_energy_components": (c_int, [c_void_p, POINTER(c_double)]),
+    "mb4_ensemble_member_stats": (c_int, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int32)]),
+    "mb4_ensemble_set_region": (c_int, [c_void_p, c_int32]),
+    "mb4_ensemble_region": (c_int32, [c_void_p]),
+    "mb4_ensemble_tune": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_double)]),
     "mb4_strerror": (c_char_p, [c_int]),
     "mb4_error_detail": (c_char_p, []),
 }
@@ -310,6 +329,137 @@ class MB4State:
         if getattr(self, "_h", None) is not None:
             mb4_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Ensembles (mb4_ensemble_*).
+
+def mb4_ensemble_create(lattices, potentials, gs, hs, opt: mb4_options | None = None) -> int:
+    n = len(lattices)
+    if not (len(potentials) == len(gs) == len(hs) == n):
+        raise ValueError("lattices, potentials, gs and hs must have the same length")
+    lats = (mb4_lattice * n)(*lattices)
+    pots = [np.ascontiguousarray(v, dtype=np.float64) for v in potentials]
+    for lat, v in zip(lattices, pots):
+        if v.size != lat.nx * lat.ny:
+            raise ValueError("potential size does not match its lattice")
+    ptrs = (POINTER(c_double) * n)(*[v.ctypes.data_as(POINTER(c_double)) for v in pots])
+    nls = (mb4_nonlinearity * n)(*[mb4_nonlinearity(float(g)) for g in gs])
+    hh = (c_double * n)(*[float(h) for h in hs])
+    out = c_void_p()
+    _check(load_library().mb4_ensemble_create(n, lats, ptrs, nls, hh,
+                                              byref(opt) if opt is not None else None,
+                                              byref(out)), "mb4_ensemble_create")
+    return out.value
+
+
+class MB4Ensemble:
+    """Owning wrapper of one mb4_ensemble.  members: sequence of objects with
+    nx, ny, g, h, t_hop and diag_shift (e.g. lattice_inputs.LatticeProblem);
+    potentials: one array of nx*ny values per member."""
+
+    def __init__(self, members, potentials, eps: float = 0.0, max_newton: int = 0,
+                 inner_sweeps: int = 0, stream: int | None = None, mem_budget: int = 0,
+                 graphs: bool = True, relative_eps: bool = False):
+        self.shapes = [(int(m.nx), int(m.ny)) for m in members]
+        opt = mb4_options_default()
+        if eps:
+            opt.eps = eps
+        if max_newton:
+            opt.max_newton = max_newton
+        if inner_sweeps:
+            opt.inner_sweeps = inner_sweeps
+        opt.stream = stream
+        opt.mem_budget = mem_budget
+        opt.flags = ((0 if graphs else MB4_FLAG_NO_GRAPHS) |
+                     (MB4_FLAG_RELATIVE_EPS if relative_eps else 0))
+        lats = [mb4_lattice(nx, ny, float(getattr(m, "t_hop", 1.0)),
+                            float(getattr(m, "diag_shift", 0.0)))
+                for (nx, ny), m in zip(self.shapes, members)]
+        self._e = mb4_ensemble_create(lats, potentials, [m.g for m in members],
+                                      [m.h for m in members], opt)
+
+    @property
+    def handle(self):
+        return self._e
+
+    def __len__(self) -> int:
+        return len(self.shapes)
+
+    def set_state(self, member: int, p, q) -> None:
+        nx, ny = self.shapes[member]
+        pp = _host(p, nx * ny)
+        qq = _host(q, nx * ny)
+        _check(load_library().mb4_ensemble_set_state(
+            self._e, member, pp.ctypes.data_as(POINTER(c_double)),
+            qq.ctypes.data_as(POINTER(c_double))), "mb4_ensemble_set_state")
+
+    def get_state(self, member: int) -> tuple[np.ndarray, np.ndarray]:
+        nx, ny = self.shapes[member]
+        p = np.empty(nx * ny)
+        q = np.empty(nx * ny)
+        _check(load_library().mb4_ensemble_get_state(
+            self._e, member, p.ctypes.data_as(POINTER(c_double)),
+            q.ctypes.data_as(POINTER(c_double))), "mb4_ensemble_get_state")
+        return p, q
+
+    def psi(self, member: int) -> np.ndarray:
+        p, q = self.get_state(member)
+        return p + 1j * q
+
+    def step(self, nsteps: int) -> int:
+        """Advances every member; returns the status code (MB4_ENOCONV keeps
+        each member's last accepted step)."""
+        return load_library().mb4_ensemble_step(self._e, int(nsteps))
+
+    def energy_components(self) -> np.ndarray:
+        """(members, 6) array: H, U_K, U_I, U_E, sum |psi|^2, sum |psi|^4."""
+        out = np.empty(6 * len(self.shapes))
+        _check(load_library().mb4_ensemble_energy_components(
+            self._e, out.ctypes.data_as(POINTER(c_double))), "mb4_ensemble_energy_components")
+        return out.reshape(-1, 6)
+
+    def energies(self) -> np.ndarray:
+        return self.energy_components()[:, 0]
+
+    def member_stats(self, member: int) -> dict:
+        done = c_int64()
+        iters = c_int32()
+        _check(load_library().mb4_ensemble_member_stats(self._e, member, byref(done),
+                                                        byref(iters)),
+               "mb4_ensemble_member_stats")
+        return {"steps_done": done.value, "newton_iters": iters.value}
+
+    def set_region(self, region: int) -> None:
+        _check(load_library().mb4_ensemble_set_region(self._e, region), "mb4_ensemble_set_region")
+
+    def region(self) -> int:
+        return load_library().mb4_ensemble_region(self._e)
+
+    def tune(self, steps: int = 32) -> tuple[int, list[float]]:
+        """Autotuner: (chosen region, ms per step of each region or -1)."""
+        best = c_int32()
+        ms = (c_double * MB4_REGION_COUNT)()
+        _check(load_library().mb4_ensemble_tune(self._e, int(steps), byref(best), ms),
+               "mb4_ensemble_tune")
+        return best.value, list(ms)
+
+    def close(self) -> None:
+        if getattr(self, "_e", None) is not None:
+            load_library().mb4_ensemble_destroy(self._e)
+            self._e = None
 
     def __enter__(self):
         return self

@@ -224,3 +224,73 @@ def test_gauss_legendre_tables_reproduce_E_and_the_cubic_integrals():
     cub5 = np.einsum("iq,qa,qb,qd->iabd", a5, l5, l5, l5)
     err = np.max(np.abs(cub5 - k.cubic), axis=(1, 2, 3))
     assert err[0] > 1e-6 and err[1] > 1e-6 and err[2] < 1e-12
+
+
+def _ens_create(lib, count=2, lats=None, pots=None, gs=None, hs=None, opt=None,
+                null=None):
+    lats = lats if lats is not None else [M.mb4_lattice(8, 8, 1.0, 0.0)] * count
+    pots = pots if pots is not None else [np.zeros(l.nx * l.ny) for l in lats]
+    gs = gs if gs is not None else [1.0] * len(lats)
+    hs = hs if hs is not None else [0.01] * len(lats)
+    n = len(lats)
+    c_lats = (M.mb4_lattice * max(n, 1))(*lats)
+    c_pots = (ctypes.POINTER(ctypes.c_double) * max(n, 1))(
+        *[p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p is not None else None
+          for p in pots])
+    c_nls = (M.mb4_nonlinearity * max(n, 1))(*[M.mb4_nonlinearity(g) for g in gs])
+    c_h = (ctypes.c_double * max(n, 1))(*hs)
+    args = [count, c_lats, c_pots, c_nls, c_h]
+    if null is not None:
+        args[null] = None
+    out = ctypes.c_void_p(1234)
+    rc = lib.mb4_ensemble_create(*args, ctypes.byref(opt) if opt is not None else None,
+                                 ctypes.byref(out))
+    return rc, out
+
+
+@pytest.mark.parametrize("case", [
+    dict(count=0, lats=[]),
+    dict(count=65537),
+    dict(null=1), dict(null=2), dict(null=3), dict(null=4),
+    dict(lats=[M.mb4_lattice(8, 8, 1.0, 0.0), M.mb4_lattice(2, 8, 1.0, 0.0)]),
+    dict(lats=[M.mb4_lattice(8, 8, float("nan"), 0.0), M.mb4_lattice(8, 8, 1.0, 0.0)]),
+    dict(gs=[1.0, float("inf")]),
+    dict(hs=[0.01, 0.0]),
+    dict(pots=[np.zeros(64), np.array([0.0] * 63 + [float("nan")])]),
+    dict(pots=[np.zeros(64), None]),
+])
+def test_ensemble_create_rejects_invalid_arguments(lib, case):
+    rc, out = _ens_create(lib, **case)
+    assert rc == M.MB4_EINVAL
+    assert out.value is None
+    assert M.error_detail() != ""
+
+
+@pytest.mark.parametrize("field,value", [("inner_sweeps", 5), ("eps", -1.0),
+                                         ("max_newton", 1001), ("flags", 4)])
+def test_ensemble_create_rejects_invalid_options(lib, field, value):
+    opt = M.mb4_options_default()
+    setattr(opt, field, value)
+    rc, _ = _ens_create(lib, opt=opt)
+    assert rc == M.MB4_EINVAL
+
+
+def test_ensemble_memory_budget_is_enforced_before_allocation(lib):
+    opt = M.mb4_options_default()
+    opt.mem_budget = 4096   # below 216 bytes/site * 128 sites
+    rc, out = _ens_create(lib, opt=opt)
+    assert rc == M.MB4_ENOMEM
+    assert out.value is None
+
+
+def test_ensemble_calls_reject_null(lib):
+    assert lib.mb4_ensemble_step(None, 1) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_set_state(None, 0, None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_get_state(None, 0, None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_energy_components(None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_member_stats(None, 0, None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_set_region(None, 0) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_tune(None, 1, None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_size(None) == -1
+    assert lib.mb4_ensemble_region(None) == -1
+    lib.mb4_ensemble_destroy(None)
