@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import numpy as np  # noqa: E402
+
 import lattice_inputs as L  # noqa: E402
 
 METRIC = "lattice-site-steps/s (FP64 MB4) at energy drift≤1e-14"
@@ -115,6 +117,109 @@ def cpu_baseline(sample_side: int, sample_steps: int, workload: str) -> dict:
                        f"{dt:.1f} s")}
 
 
+def step_bytes_per_site(iters: int) -> int:
+    """Algorithmic HBM bytes per site of one whole step with `iters` Newton
+    iterations: first solve, fused iterations, final update."""
+    return (BYTES_PER_SITE["stage_solve_first"] + BYTES_PER_SITE["iterate_first"] * (iters >= 2) +
+            BYTES_PER_SITE["iterate"] * max(iters - 2, 0) + BYTES_PER_SITE["final_update"])
+
+
+def run_ensemble(args, torch, M) -> int:
+    """The disorder ensemble: args.members realisations of 128^2 advanced
+    together by mb4_ensemble_step, after the region autotuner."""
+    members = L.ensemble(args.members)
+    inputs = [L.make_inputs(m) for m in members]
+    steps = args.steps if args.steps is not None else L.ENSEMBLE_STEPS
+    ens = M.MB4Ensemble(members, [v for v, _, _ in inputs], eps=args.eps,
+                        inner_sweeps=args.sweeps)
+    for i, (_, p, q) in enumerate(inputs):
+        ens.set_state(i, p, q)
+    h_start = ens.energies()
+    tuning = None
+    if args.tune_steps > 0:
+        best, ms = ens.tune(args.tune_steps)
+        tuning = {"region": M.REGION_NAMES[best],
+                  "ms_per_step": {M.REGION_NAMES[r]: (t if t >= 0 else None)
+                                  for r, t in enumerate(ms)}}
+    if args.warmup:
+        if ens.step(args.warmup) != M.MB4_OK:
+            raise RuntimeError(f"warmup failed: {M.error_detail()}")
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    t0 = time.perf_counter()
+    chunk = max(1, steps // 20)
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        if ens.step(n) != M.MB4_OK:
+            raise RuntimeError(f"ensemble step failed: {M.error_detail()}")
+        done += n
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    event_ms = ev0.elapsed_time(ev1)
+    h_end = ens.energies()
+    drift = float(np.max(np.abs(h_end - h_start) / np.abs(h_start)))
+    iters = [ens.member_stats(i)["newton_iters"] for i in range(len(members))]
+    ens.close()
+    sites = sum(m.nx * m.ny for m in members)
+    it = max(iters)
+    step_bytes = step_bytes_per_site(it) * sites
+    result = {
+        "metric": METRIC, "value": sites * steps / elapsed, "unit": UNIT, "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / steps,
+        "ms_per_step_hip_events": event_ms / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded disorder realisations 1000 + r, defects, wavepackets)",
+        "config": {"workload": "ensemble128", "members": len(members), "nx": 128, "ny": 128,
+                   "h": members[0].h, "g": members[0].g, "disorder_w": members[0].disorder_w,
+                   "defects": members[0].defect_count, "defect_v": members[0].defect_v,
+                   "sigma": members[0].sigma, "seeds": f"1000..{999 + len(members)}",
+                   "parallelism": "single GPU, all members per launch",
+                   "newton_eps": args.eps or 1e-13, "newton_test": "absolute (Algorithm 1)"},
+        "energy_drift": drift, "energy_drift_ok": drift <= 1e-14,
+        "newton_iters_last": {"min": min(iters), "max": it},
+        "tuning": tuning,
+        "step_bandwidth": {"bytes_per_site_step": step_bytes_per_site(it),
+                           "achieved_GBs": step_bytes / (elapsed / steps) / 1e9,
+                           "peak_GBs": HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_member(args.cpu_member_steps)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def cpu_baseline_member(sample_steps: int) -> dict:
+    """The oracle as it stands, single-threaded, on realisation 0 of the
+    ensemble for sample_steps steps."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    cfg = L.ensemble_member(0, steps=sample_steps)
+    v, p, q = L.make_inputs(cfg)
+    orc = O.oracle_for(cfg, v, solver="gmres")
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        t0 = time.perf_counter()
+        u = p + 1j * q
+        for _ in range(sample_steps):
+            u = orc.step(u)
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return {"value": cfg.sites * sample_steps / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": (f"ensemble realisation 0 (128x128), {sample_steps} steps, gmres stage "
+                       f"solves, 1 thread, {dt:.1f} s")}
+
+
 def copy_calibration(mib: int) -> int:
     """Five plain device-to-device copies of `mib` MiB: each moves exactly
     mib MiB in and mib MiB out of HBM, which calibrates the FETCH_SIZE and
@@ -135,12 +240,19 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="lattice2048", choices=sorted(L.CONFIGS))
+    ap.add_argument("--workload", default="lattice2048",
+                    choices=sorted(L.CONFIGS) + ["ensemble128"])
+    ap.add_argument("--members", type=int, default=L.ENSEMBLE_SIZE,
+                    help="ensemble128: number of realisations")
+    ap.add_argument("--tune-steps", type=int, default=32,
+                    help="ensemble128: steps the region autotuner times per shape (0: no tuning)")
     ap.add_argument("--eps", type=float, default=0.0, help="Newton tolerance (0: library default)")
     ap.add_argument("--sweeps", type=int, default=0, help="block-Jacobi sweeps (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=1024)
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-member-steps", type=int, default=60,
+                    help="ensemble128: oracle steps on one realisation for cpu_baseline")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel events (no roofline entry)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -161,6 +273,8 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "ensemble128":
+        return run_ensemble(args, torch, M)
     cfg = L.CONFIGS[args.workload]
     steps = args.steps if args.steps is not None else cfg.steps
     v, p, q = L.make_inputs(cfg)

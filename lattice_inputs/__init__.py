@@ -174,6 +174,16 @@ def ensemble_member(r: int, side: int = 128, steps: int = 5000) -> LatticeProble
         sigma=8.0, kx=math.pi / 4, ky=0.0, h=0.01, steps=steps, seed=1000 + r)
 
 
+# The disorder ensemble: ENSEMBLE_SIZE realisations of ensemble_member, each
+# run for ENSEMBLE_STEPS steps.
+ENSEMBLE_SIZE = 512
+ENSEMBLE_STEPS = 5000
+
+
+def ensemble(size: int = ENSEMBLE_SIZE) -> list[LatticeProblem]:
+    return [ensemble_member(r) for r in range(size)]
+
+
 def config(name: str, **overrides) -> LatticeProblem:
     """A copy of a named workload with some fields replaced."""
     base = CONFIGS[name].as_dict()

@@ -652,11 +652,12 @@ int mb4_ensemble_tune(mb4_ensemble* e, int32_t steps, int32_t* best, double* ms_
   double times[mb4::kRegionCount];
   int chosen = region0;
   double best_ms = -1.0;
+  // Member states and counters go back after every trial; the iteration
+  // prediction learnt in the untimed pass is kept for the timed one, and
+  // reset at the end.
   auto restore = [&]() -> hipError_t {
     e->steps_done = done0;
     e->last_iters = iters0;
-    e->predicted = pred0;
-    e->lower_batches = lower0;
     return hipMemcpyAsync(e->u0, backup, field, hipMemcpyDeviceToDevice, e->stream);
   };
   hipError_t err = hipMemcpyAsync(backup, e->u0, field, hipMemcpyDeviceToDevice, e->stream);
@@ -693,6 +694,8 @@ int mb4_ensemble_tune(mb4_ensemble* e, int32_t steps, int32_t* best, double* ms_
   }
   const int rc_sel = mb4_ensemble_set_region(e, rc == MB4_OK ? chosen : region0);
   if (rc != MB4_OK) (void)restore();
+  e->predicted = pred0;
+  e->lower_batches = lower0;
   (void)hipStreamSynchronize(e->stream);
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
