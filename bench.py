@@ -57,6 +57,17 @@ BYTES_PER_SITE = {
     "iterate_first": 168,
     "iterate": 216,
 }
+# With FP32 inner solves the stage corrections rbar are 24 B/site instead of 48:
+#   stage_solve_first: u0 16 + V 8 -> rbar 24
+#   iterate_first:     u0 16 + V 8 + rbar 24 -> U 48 + rbar 24
+#   iterate:           u0 16 + V 8 + U 48 + rbar 24 -> U 48 + rbar 24
+#   final_update:      U_3 16 + rbar 24 -> u0 16
+BYTES_PER_SITE_FP32 = {
+    "stage_solve_first": 48,
+    "iterate_first": 120,
+    "iterate": 168,
+    "final_update": 56,
+}
 
 
 def kernel_source_digest() -> str:
@@ -117,11 +128,12 @@ def cpu_baseline(sample_side: int, sample_steps: int, workload: str) -> dict:
                        f"{dt:.1f} s")}
 
 
-def step_bytes_per_site(iters: int) -> int:
+def step_bytes_per_site(iters: int, fp32_solve: bool = False) -> int:
     """Algorithmic HBM bytes per site of one whole step with `iters` Newton
     iterations: first solve, fused iterations, final update."""
-    return (BYTES_PER_SITE["stage_solve_first"] + BYTES_PER_SITE["iterate_first"] * (iters >= 2) +
-            BYTES_PER_SITE["iterate"] * max(iters - 2, 0) + BYTES_PER_SITE["final_update"])
+    b = BYTES_PER_SITE_FP32 if fp32_solve else BYTES_PER_SITE
+    return (b["stage_solve_first"] + b["iterate_first"] * (iters >= 2) +
+            b["iterate"] * max(iters - 2, 0) + b["final_update"])
 
 
 def run_ensemble(args, torch, M) -> int:
@@ -131,7 +143,7 @@ def run_ensemble(args, torch, M) -> int:
     inputs = [L.make_inputs(m) for m in members]
     steps = args.steps if args.steps is not None else L.ENSEMBLE_STEPS
     ens = M.MB4Ensemble(members, [v for v, _, _ in inputs], eps=args.eps,
-                        inner_sweeps=args.sweeps)
+                        inner_sweeps=args.sweeps, fp32_solve=args.fp32_solve)
     for i, (_, p, q) in enumerate(inputs):
         ens.set_state(i, p, q)
     h_start = ens.energies()
@@ -166,12 +178,13 @@ def run_ensemble(args, torch, M) -> int:
     ens.close()
     sites = sum(m.nx * m.ny for m in members)
     it = max(iters)
-    step_bytes = step_bytes_per_site(it) * sites
+    step_bytes = step_bytes_per_site(it, args.fp32_solve) * sites
     result = {
         "metric": METRIC, "value": sites * steps / elapsed, "unit": UNIT, "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / steps,
         "ms_per_step_hip_events": event_ms / steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (f32 inner solves)" if args.fp32_solve else "f64",
         "data": "synthetic (seeded disorder realisations 1000 + r, defects, wavepackets)",
         "config": {"workload": "ensemble128", "members": len(members), "nx": 128, "ny": 128,
                    "h": members[0].h, "g": members[0].g, "disorder_w": members[0].disorder_w,
@@ -182,7 +195,7 @@ def run_ensemble(args, torch, M) -> int:
         "energy_drift": drift, "energy_drift_ok": drift <= 1e-14,
         "newton_iters_last": {"min": min(iters), "max": it},
         "tuning": tuning,
-        "step_bandwidth": {"bytes_per_site_step": step_bytes_per_site(it),
+        "step_bandwidth": {"bytes_per_site_step": step_bytes_per_site(it, args.fp32_solve),
                            "achieved_GBs": step_bytes / (elapsed / steps) / 1e9,
                            "peak_GBs": HBM_PEAK_GBS},
     }
@@ -248,6 +261,8 @@ def main(argv=None) -> int:
                     help="ensemble128: steps the region autotuner times per shape (0: no tuning)")
     ap.add_argument("--eps", type=float, default=0.0, help="Newton tolerance (0: library default)")
     ap.add_argument("--sweeps", type=int, default=0, help="block-Jacobi sweeps (0: default)")
+    ap.add_argument("--fp32-solve", action="store_true",
+                    help="FP32 inner stage solves inside the FP64 Newton loop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=1024)
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
@@ -279,7 +294,7 @@ def main(argv=None) -> int:
     steps = args.steps if args.steps is not None else cfg.steps
     v, p, q = L.make_inputs(cfg)
     st = M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, t_hop=cfg.t_hop, diag_shift=cfg.diag_shift,
-                    eps=args.eps, inner_sweeps=args.sweeps)
+                    eps=args.eps, inner_sweeps=args.sweeps, fp32_solve=args.fp32_solve)
     st.set_state(p, q)
     h_start = st.energy()
     if args.warmup:
@@ -337,7 +352,7 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 (f32 inner solves)" if args.fp32_solve else "f64",
         "data": "synthetic (seeded disorder, defects and Gaussian wavepacket)",
         "config": {"workload": cfg.name, "nx": cfg.nx, "ny": cfg.ny, "h": cfg.h, "g": cfg.g,
                    "disorder_w": cfg.disorder_w, "defects": cfg.defect_count,
@@ -354,9 +369,10 @@ def main(argv=None) -> int:
         dominant = max(prof, key=lambda k: prof[k][1])
         n_launch, total_ms = prof[dominant]
         per_launch_s = total_ms / 1e3 / max(n_launch, 1)
-        bytes_launch = BYTES_PER_SITE[dominant] * sites
+        table = BYTES_PER_SITE_FP32 if args.fp32_solve else BYTES_PER_SITE
+        bytes_launch = table[dominant] * sites
         achieved = bytes_launch / per_launch_s / 1e9
-        traffic = measured_traffic(dominant, sites)
+        traffic = None if args.fp32_solve else measured_traffic(dominant, sites)
         result["roofline"] = {
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -93,6 +93,14 @@ typedef struct {
 /* mb4_options.flags: read eps relative to ||u_0||_inf of each step instead of
  * as an absolute bound (for states whose amplitude is far from 1). */
 #define MB4_FLAG_RELATIVE_EPS 2u
+/* mb4_options.flags: FP32 inner stage solves.  The block-Jacobi sweeps of
+ * the stage systems (Eq. MB4_5), their 2x2 block inverses and right-hand
+ * sides run in FP32 and the stage corrections rbar are stored in FP32; the
+ * residual Phi, the stage quadrature, the Newton update U + (T (x) I) rbar,
+ * its norm and the energy stay FP64, so the step converges to the same FP64
+ * root.  At most 4 inner sweeps; mb4_newton_update and mb4_stage_solve stay
+ * FP64. */
+#define MB4_FLAG_FP32_SOLVE 4u
 
 typedef struct mb4_state mb4_state;
 
@@ -266,7 +274,8 @@ MB4_API int mb4_ensemble_energy_components(mb4_ensemble* ens, double* out);
 MB4_API int mb4_ensemble_member_stats(const mb4_ensemble* ens, int32_t member,
                                       int64_t* steps_done, int32_t* newton_iters);
 
-/* Selects the solve-region shape (MB4_REGION_*). */
+/* Selects the solve-region shape (MB4_REGION_*); with MB4_FLAG_FP32_SOLVE
+ * only MB4_REGION_32x32 is built. */
 MB4_API int mb4_ensemble_set_region(mb4_ensemble* ens, int32_t region);
 MB4_API int32_t mb4_ensemble_region(const mb4_ensemble* ens);
 

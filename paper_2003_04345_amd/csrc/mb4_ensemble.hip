@@ -69,6 +69,7 @@ struct mb4_ensemble {
   size_t total = 0;              // sites of all members
   double eps = kDefaultEps;
   bool relative_eps = false;
+  bool fp32 = false;  // FP32 inner stage solves (32 x 32 regions only)
   int max_newton = kDefaultMaxNewton;
   int sweeps = kDefaultSweeps;
   int rec_len = 0;
@@ -169,7 +170,8 @@ void member_blocks(const mb4_ensemble* e, const MemberDesc& d, int out[4]) {
   out[kEnergy] = tiles(d.nx, tx) * tiles(d.ny, ty);
 }
 
-bool region_usable(int region, int sweeps) {
+bool region_usable(int region, int sweeps, bool fp32) {
+  if (fp32 && region != mb4::kRegion32x32) return false;
   int tx, ty, ix, iy;
   mb4::first_solve_tile(region, sweeps, &tx, &ty);
   mb4::iterate_tile(region, sweeps, &ix, &iy);
@@ -231,7 +233,7 @@ int enqueue_step(mb4_ensemble* e, int step, int iters) {
               mfin = multi_of(e, kFinal, step);
   HIP_TRY(mb4::launch_first_solve(L, pp(r_planes(e, 1)), e->sweeps, rec + 1, rec,
                                   Planes3{{nullptr, nullptr, nullptr}}, e->q, {}, mf,
-                                  e->region));
+                                  e->region, e->fp32));
   for (int l = 2; l <= iters; ++l) {
     const int j = l - 1;
     const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
@@ -239,14 +241,14 @@ int enqueue_step(mb4_ensemble* e, int step, int iters) {
     const CPlanes3 uin = j >= 2 ? cp(u_planes(e, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
     HIP_TRY(mb4::launch_iterate(L, uin, pp(u_planes(e, j)), cp(r_planes(e, j)),
                                 pp(r_planes(e, l)), j == 1, e->sweeps, rec + l, chk, fin, e->u0,
-                                e->q, {}, mi, e->region));
+                                e->q, {}, mi, e->region, e->fp32));
   }
   const int j = iters;
   const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
   const ConvCheck fin = conv_check(e, rec, j);
   const CPlanes3 uin = j >= 2 ? cp(u_planes(e, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
   HIP_TRY(mb4::launch_final_update(L, uin, cp(r_planes(e, j)), j == 1, chk, fin, e->u0, e->q,
-                                   {}, mfin));
+                                   {}, mfin, e->fp32));
   return MB4_OK;
 }
 
@@ -422,7 +424,7 @@ int mb4_ensemble_create(int32_t count, const mb4_lattice* lattices,
     if (opt->inner_sweeps < 0 || opt->inner_sweeps > mb4::kMaxFusedSweeps)
       return fail(MB4_EINVAL, "inner_sweeps of an ensemble must be in [0, %d]",
                   mb4::kMaxFusedSweeps);
-    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS)) != 0)
+    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS | MB4_FLAG_FP32_SOLVE)) != 0)
       return fail(MB4_EINVAL, "unknown bits in flags");
     if (opt->eps > 0.0) o.eps = opt->eps;
     if (opt->max_newton > 0) o.max_newton = opt->max_newton;
@@ -471,6 +473,7 @@ int mb4_ensemble_create(int32_t count, const mb4_lattice* lattices,
   e->total = total;
   e->eps = o.eps;
   e->relative_eps = (o.flags & MB4_FLAG_RELATIVE_EPS) != 0;
+  e->fp32 = (o.flags & MB4_FLAG_FP32_SOLVE) != 0;
   e->max_newton = o.max_newton;
   e->sweeps = o.inner_sweeps;
   e->rec_len = o.max_newton + 1;
@@ -617,7 +620,7 @@ int mb4_ensemble_set_region(mb4_ensemble* e, int32_t region) {
   if (rc != MB4_OK) return rc;
   if (region < 0 || region >= mb4::kRegionCount)
     return fail(MB4_EINVAL, "region must be in [0, %d)", int(mb4::kRegionCount));
-  if (!region_usable(region, e->sweeps))
+  if (!region_usable(region, e->sweeps, e->fp32))
     return fail(MB4_EINVAL, "region %s leaves no tile at %d sweeps", mb4::region_name(region),
                 e->sweeps);
   if (region == e->region) return MB4_OK;
@@ -666,7 +669,7 @@ int mb4_ensemble_tune(mb4_ensemble* e, int32_t steps, int32_t* best, double* ms_
   if (err != hipSuccess) rc = fail(MB4_EDEVICE, "tune setup: %s", hipGetErrorString(err));
   for (int r = 0; r < mb4::kRegionCount && rc == MB4_OK; ++r) {
     times[r] = -1.0;
-    if (!region_usable(r, e->sweeps)) continue;
+    if (!region_usable(r, e->sweeps, e->fp32)) continue;
     rc = mb4_ensemble_set_region(e, r);
     // One untimed pass (graph capture, caches), then the timed one.
     if (rc == MB4_OK) rc = mb4_ensemble_step(e, std::min<int64_t>(steps, kBatch));

@@ -25,13 +25,20 @@ struct Lattice {
   const double2* u0;   // [nx*ny] (p, q)
 };
 
-struct Planes3 {
-  double2* s[3];
+// Three planes of a stage field (element type double2, or float2 for the
+// stage corrections of the FP32 inner solves).
+template <class T2>
+struct PlanesOf {
+  T2* s[3];
 };
 
-struct CPlanes3 {
-  const double2* s[3];
+template <class T2>
+struct CPlanesOf {
+  const T2* s[3];
 };
+
+using Planes3 = PlanesOf<double2>;
+using CPlanes3 = CPlanesOf<double2>;
 
 // Convergence test of Newton iteration `prev`:
 // ||r^prev||_inf <= eps * max(||u_0||_inf, DBL_MIN).  Kernels of iteration l
@@ -91,6 +98,13 @@ hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 // not NULL: the Lattice then carries ensemble-wide V and u0, planes and
 // records are those of member 0, and `region` picks the solve-region shape.
 // Members with todo[m] <= mu.step do nothing.
+//
+// fp32: the FP32 inner stage solves.  The stage corrections rbar (rout, rbar)
+// are float2 planes (the Planes3 pointers are reinterpreted), and the
+// block-Jacobi sweeps, the 2x2 block inverses and the right-hand side -Phibar
+// are rounded to and computed in FP32.  The residual Phi, the stage
+// quadrature, the update U + (T (x) I) rbar and the norms stay FP64.  Only
+// the 32 x 32 region exists in this precision.
 
 // Newton iteration 1, stage solve: `sweeps` (1..4) block-Jacobi sweeps of
 // (I - h lambda_i J) r_i = -Phibar_i with Phibar_i = -h TC_i f(u_0) (the
@@ -100,7 +114,8 @@ hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
                               Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {},
-                              const Multi& mu = {}, int region = kRegion32x32);
+                              const Multi& mu = {}, int region = kRegion32x32,
+                              bool fp32 = false);
 
 // Newton iteration l >= 2 (or a kernel-level call), stage solve: `sweeps`
 // (1..4) block-Jacobi sweeps from r = 0 for the three stage systems
@@ -141,13 +156,14 @@ hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlane
                           Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
                           ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
                           LaunchEvents ev = {}, const Multi& mu = {},
-                          int region = kRegion32x32);
+                          int region = kRegion32x32, bool fp32 = false);
 
 // Update pass of the last iteration of a batch: the final update of u0_out if
 // `fin` holds and `check` does not; nothing otherwise.
 hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
                                ConvCheck check, ConvCheck fin, double2* u0_out,
-                               hipStream_t stream, LaunchEvents ev = {}, const Multi& mu = {});
+                               hipStream_t stream, LaunchEvents ev = {}, const Multi& mu = {},
+                               bool fp32 = false);
 
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -385,6 +385,56 @@ __device__ __forceinline__ double2 block_solve(const SiteBlock& s, double hl, do
                       inv * ((1.0 - hl * s.a) * bq - hl * s.cc * bp));
 }
 
+// Precision of the stage corrections and of the sweeps: RT = double, or
+// float for the FP32 inner solves (everything else stays FP64).
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+template <class T>
+using vec2_t = typename Vec2<T>::type;
+
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+
+template <class T>
+__device__ __forceinline__ vec2_t<T> vec2(T x, T y) {
+  vec2_t<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+
+template <class T>
+struct SiteBlockT {
+  T a, bb, cc;
+};
+
+template <class T>
+__device__ __forceinline__ SiteBlockT<T> block_in(const SiteBlock& s) {
+  return SiteBlockT<T>{T(s.a), T(s.bb), T(s.cc)};
+}
+
+// As block_solve, in precision T.
+template <class T>
+__device__ __forceinline__ vec2_t<T> block_solve_t(const SiteBlockT<T>& s, T hl, T inv, T bp,
+                                                   T bq) {
+  return vec2<T>(inv * ((T(1) + hl * s.a) * bp + hl * s.bb * bq),
+                 inv * ((T(1) - hl * s.a) * bq - hl * s.cc * bp));
+}
+
+// 1 / det(I - hl J_site) in precision T.
+template <class T>
+__device__ __forceinline__ T block_inv(const SiteBlockT<T>& s, T hl) {
+  return T(1) / (T(1) + hl * hl * (s.bb * s.cc - s.a * s.a));
+}
+
 // f(u_0) = S grad H = (A q + g n q, -(A p + g n p)) at one site, from u and
 // its four neighbours a, b (x -/+ 1), d, e (y -/+ 1).
 __device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v, double2 a,
@@ -423,12 +473,14 @@ struct FirstArgs {
   bool store_rhs;                  // also write Phibar of the tile
 };
 
-template <int RX, int RY, int H, bool FIRST>
-__global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
-                                                              Planes3 phib_out, Planes3 rout,
+template <int RX, int RY, int H, bool FIRST, class RT>
+__global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
+                                                              Planes3 phib_out,
+                                                              PlanesOf<vec2_t<RT>> rout,
                                                               unsigned long long* rslot,
                                                               ConvCheck chk, FirstArgs fa,
                                                               Multi mu) {
+  using R2 = vec2_t<RT>;
   constexpr int kSolveThreads = RX * RY / 2;
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
   if (w.skip) return;
@@ -444,7 +496,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
   constexpr int PER = RN / kSolveThreads;
   static_assert(RN % kSolveThreads == 0, "region must be a whole number of passes");
   constexpr int UX = RX + 2, UN = FIRST ? UX * (RY + 2) : 1;
-  __shared__ double2 sr[3][RN];
+  __shared__ R2 sr[3][RN];
   __shared__ double2 su[UN];
   const int nx = L.nx, ny = L.ny;
   int tx0, ty0;
@@ -471,9 +523,9 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
     __syncthreads();
   }
 
-  double2 rhs[PER][3];
-  SiteBlock blk[PER];
-  double inv[PER][3];
+  R2 rhs[PER][3];
+  SiteBlockT<RT> blk[PER];
+  RT inv[PER][3];
   unsigned long long um = 0ull;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
@@ -483,7 +535,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
     const int e = (ly + 1) * UX + lx + 1;
     const double2 u = FIRST ? su[e] : L.u0[site];
     const double v = vv[j];
-    blk[j] = site_block(L, u, v);
+    blk[j] = block_in<RT>(site_block(L, u, v));
     double2 f = make_double2(0.0, 0.0);
     if (FIRST) {
       f = f_from(L, u, v, su[e - 1], su[e + 1], su[e - UX], su[e + UX]);
@@ -493,16 +545,16 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double hl = L.h * MB4_LAMBDA[i];
+      const RT hl = RT(L.h * MB4_LAMBDA[i]);
       if (FIRST) {
         const double k = L.h * MB4_TC[i];
-        rhs[j][i] = make_double2(k * f.x, k * f.y);
+        rhs[j][i] = vec2<RT>(RT(k * f.x), RT(k * f.y));
       } else {
         const double2 ph = phib_in.s[i][site];
-        rhs[j][i] = make_double2(-ph.x, -ph.y);
+        rhs[j][i] = vec2<RT>(RT(-ph.x), RT(-ph.y));
       }
-      inv[j][i] = 1.0 / (1.0 + hl * hl * (blk[j].bb * blk[j].cc - blk[j].a * blk[j].a));
-      sr[i][idx] = block_solve(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
+      inv[j][i] = block_inv(blk[j], hl);
+      sr[i][idx] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
     }
   }
   // Sweeps 2 .. H+1, one stage at a time so that only one stage's new values
@@ -510,13 +562,13 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
   // previous stage's new values are stored (every read of that buffer is
   // done) and stage i is computed from LDS (its buffer was last stored before
   // at least one earlier barrier).
-  double2 rn[PER];
+  R2 rn[PER];
 #pragma unroll
   for (int s = 0; s < H; ++s) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double hl = L.h * MB4_LAMBDA[i];
-      const double ht = hl * L.t;
+      const RT hl = RT(L.h * MB4_LAMBDA[i]);
+      const RT ht = hl * RT(L.t);
       __syncthreads();
       if (s > 0 || i > 0) {
         const int ip = i == 0 ? 2 : i - 1;
@@ -532,12 +584,12 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
         const int idx = threadIdx.x + j * kSolveThreads;
         const int lx = idx % RX, ly = idx / RX;
         if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
-          const double2 r1 = sr[i][idx - 1], r2 = sr[i][idx + 1];
-          const double2 r3 = sr[i][idx - RX], r4 = sr[i][idx + RX];
-          const double sp = (r1.x + r2.x) + (r3.x + r4.x);
-          const double sq = (r1.y + r2.y) + (r3.y + r4.y);
-          rn[j] = block_solve(blk[j], hl, inv[j][i], rhs[j][i].x - ht * sq,
-                              rhs[j][i].y + ht * sp);
+          const R2 r1 = sr[i][idx - 1], r2 = sr[i][idx + 1];
+          const R2 r3 = sr[i][idx - RX], r4 = sr[i][idx + RX];
+          const RT sp = (r1.x + r2.x) + (r3.x + r4.x);
+          const RT sq = (r1.y + r2.y) + (r3.y + r4.y);
+          rn[j] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x - ht * sq,
+                                rhs[j][i].y + ht * sp);
         }
       }
     }
@@ -564,10 +616,11 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
       double2 r[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        r[i] = sr[i][idx];
-        rout.s[i][gsite[j]] = r[i];
+        const R2 ri = sr[i][idx];
+        rout.s[i][gsite[j]] = ri;
+        r[i] = to_d2(ri);
         if (FIRST && fa.store_rhs)
-          phib_out.s[i][gsite[j]] = make_double2(-rhs[j][i].x, -rhs[j][i].y);
+          phib_out.s[i][gsite[j]] = make_double2(-double(rhs[j][i].x), -double(rhs[j][i].y));
       }
       if (rslot != nullptr) {
 #pragma unroll
@@ -598,12 +651,14 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_stage_solve(Lattice L, CPlane
 // is written back.  As in
 // k_stage_solve, each region position computes the values of its (wrapped)
 // lattice site from region neighbours only.
-template <int RX, int RY, bool FROM_U0, int H>
-__global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 Uin, Planes3 Uout,
-                                                          CPlanes3 rb, Planes3 rout,
+template <int RX, int RY, bool FROM_U0, int H, class RT>
+__global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate(Lattice L, CPlanes3 Uin, Planes3 Uout,
+                                                          CPlanesOf<vec2_t<RT>> rb,
+                                                          PlanesOf<vec2_t<RT>> rout,
                                                           unsigned long long* rnext,
                                                           ConvCheck chk, ConvCheck fin,
                                                           double2* u0_out, Multi mu) {
+  using R2 = vec2_t<RT>;
   constexpr int kIterThreads = RX * RY / 2;
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
   if (w.skip) return;
@@ -637,7 +692,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
         const int site = (oy + ly) * nx + (ox + lx);
         double2 r[3];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
+        for (int m = 0; m < 3; ++m) r[m] = to_d2(rb.s[m][site]);
         const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
         const double2 d = t_apply(2, r);
         u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
@@ -646,7 +701,9 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
     return;
   }
 
-  __shared__ double2 sb[3][RN];  // W_i, then the stage iterates
+  // W_i (FP64), then the stage iterates (RT) in the same LDS.
+  __shared__ double2 sb[3][RN];
+  R2(*const si)[RN] = reinterpret_cast<R2(*)[RN]>(&sb[0][0]);
   int gsite[PER];
   double2 u0v[PER];
   double2 Un[PER][3];
@@ -654,7 +711,8 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
   // Phase 1: U^iter and W_i on the whole region.  Every load of both
   // positions is issued before the first store, so that their latencies
   // overlap (the compiler cannot move loads across the stores of U^iter).
-  double2 ldu[PER][3], ldr[PER][3];
+  double2 ldu[PER][3];
+  R2 ldr[PER][3];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
@@ -676,7 +734,8 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double2 base = FROM_U0 ? u0v[j] : ldu[j][i];
-      const double2 d = t_apply(i, ldr[j]);
+      const double2 rj[3] = {to_d2(ldr[j][0]), to_d2(ldr[j][1]), to_d2(ldr[j][2])};
+      const double2 d = t_apply(i, rj);
       Un[j][i] = make_double2(base.x + d.x, base.y + d.y);
     }
 #pragma unroll
@@ -696,15 +755,15 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
   __syncthreads();
 
   // Phase 2: residual, transform and first (local) sweep on ring >= 1.
-  double2 rhs[PER][3];
-  SiteBlock blk[PER];
-  double inv[PER][3];
-  double2 r1[PER][3];
+  R2 rhs[PER][3];
+  SiteBlockT<RT> blk[PER];
+  RT inv[PER][3];
+  R2 r1[PER][3];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
-    blk[j] = site_block(L, u0v[j], vv[j]);
+    blk[j] = block_in<RT>(site_block(L, u0v[j], vv[j]));
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
       const double t = L.t, g = L.g, h = L.h;
       const double vs = vv[j] + L.shift;
@@ -743,10 +802,10 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
                           MB4_TINV[i][2] * phi[2].x;
         const double bq = MB4_TINV[i][0] * phi[0].y + MB4_TINV[i][1] * phi[1].y +
                           MB4_TINV[i][2] * phi[2].y;
-        const double hl = L.h * MB4_LAMBDA[i];
-        rhs[j][i] = make_double2(-bp, -bq);
-        inv[j][i] = 1.0 / (1.0 + hl * hl * (blk[j].bb * blk[j].cc - blk[j].a * blk[j].a));
-        r1[j][i] = block_solve(blk[j], hl, inv[j][i], -bp, -bq);
+        const RT hl = RT(L.h * MB4_LAMBDA[i]);
+        rhs[j][i] = vec2<RT>(RT(-bp), RT(-bq));
+        inv[j][i] = block_inv(blk[j], hl);
+        r1[j][i] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
       }
     }
   }
@@ -757,18 +816,18 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
     const int lx = idx % RX, ly = idx / RX;
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) sb[i][idx] = r1[j][i];
+      for (int i = 0; i < 3; ++i) si[i][idx] = r1[j][i];
     }
   }
   // Sweeps 2 .. H+1 on ring >= 2, one stage at a time with one barrier per
   // stage sweep (see k_stage_solve).
-  double2 rn[PER];
+  R2 rn[PER];
 #pragma unroll
   for (int s = 0; s < H; ++s) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double hl = L.h * MB4_LAMBDA[i];
-      const double ht = hl * L.t;
+      const RT hl = RT(L.h * MB4_LAMBDA[i]);
+      const RT ht = hl * RT(L.t);
       __syncthreads();
       if (s > 0 || i > 0) {
         const int ip = i == 0 ? 2 : i - 1;
@@ -776,7 +835,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
         for (int j = 0; j < PER; ++j) {
           const int idx = threadIdx.x + j * kIterThreads;
           const int lx = idx % RX, ly = idx / RX;
-          if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) sb[ip][idx] = rn[j];
+          if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) si[ip][idx] = rn[j];
         }
       }
 #pragma unroll
@@ -784,12 +843,12 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
         const int idx = threadIdx.x + j * kIterThreads;
         const int lx = idx % RX, ly = idx / RX;
         if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) {
-          const double2 q1 = sb[i][idx - 1], q2 = sb[i][idx + 1];
-          const double2 q3 = sb[i][idx - RX], q4 = sb[i][idx + RX];
-          const double sp = (q1.x + q2.x) + (q3.x + q4.x);
-          const double sq = (q1.y + q2.y) + (q3.y + q4.y);
-          rn[j] = block_solve(blk[j], hl, inv[j][i], rhs[j][i].x - ht * sq,
-                              rhs[j][i].y + ht * sp);
+          const R2 q1 = si[i][idx - 1], q2 = si[i][idx + 1];
+          const R2 q3 = si[i][idx - RX], q4 = si[i][idx + RX];
+          const RT sp = (q1.x + q2.x) + (q3.x + q4.x);
+          const RT sq = (q1.y + q2.y) + (q3.y + q4.y);
+          rn[j] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x - ht * sq,
+                                rhs[j][i].y + ht * sp);
         }
       }
     }
@@ -800,7 +859,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
     for (int j = 0; j < PER; ++j) {
       const int idx = threadIdx.x + j * kIterThreads;
       const int lx = idx % RX, ly = idx / RX;
-      if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) sb[2][idx] = rn[j];
+      if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) si[2][idx] = rn[j];
     }
   }
   __syncthreads();
@@ -816,8 +875,9 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
       double2 r[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        r[i] = sb[i][idx];
-        rout.s[i][site] = r[i];
+        const R2 ri = si[i][idx];
+        rout.s[i][site] = ri;
+        r[i] = to_d2(ri);
       }
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
@@ -832,8 +892,9 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
 // Update pass of the last Newton iteration `fin.prev` of a batch: the final
 // update u_1 = U_3 + (T rbar)_3 (base U_3 = Uin[2], or u_0 if from_u0) if that
 // iteration met the tolerance and none before it did; nothing otherwise.
-template <bool FROM_U0>
-__global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes3 Uin, CPlanes3 rb,
+template <bool FROM_U0, class RT>
+__global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes3 Uin,
+                                                              CPlanesOf<vec2_t<RT>> rb,
                                                               ConvCheck chk, ConvCheck fin,
                                                               double2* u0_out, int n, Multi mu) {
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
@@ -849,7 +910,7 @@ __global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes
   if (site >= n) return;
   double2 r[3];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
+  for (int m = 0; m < 3; ++m) r[m] = to_d2(rb.s[m][site]);
   const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
   const double2 d = t_apply(2, r);
   u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
@@ -1081,54 +1142,72 @@ void energy_tile(int* tx, int* ty) {
 
 namespace {
 
-template <int RX, int RY, bool FIRST>
+// Planes3 pointers reinterpreted as stage corrections of precision RT.
+template <class RT>
+PlanesOf<vec2_t<RT>> as_r(Planes3 p) {
+  return PlanesOf<vec2_t<RT>>{{reinterpret_cast<vec2_t<RT>*>(p.s[0]),
+                               reinterpret_cast<vec2_t<RT>*>(p.s[1]),
+                               reinterpret_cast<vec2_t<RT>*>(p.s[2])}};
+}
+template <class RT>
+CPlanesOf<vec2_t<RT>> as_r(CPlanes3 p) {
+  return CPlanesOf<vec2_t<RT>>{{reinterpret_cast<const vec2_t<RT>*>(p.s[0]),
+                                reinterpret_cast<const vec2_t<RT>*>(p.s[1]),
+                                reinterpret_cast<const vec2_t<RT>*>(p.s[2])}};
+}
+
+template <int RX, int RY, bool FIRST, class RT>
 hipError_t launch_solve_region(const Lattice& lat, CPlanes3 phib_in, Planes3 phib_out,
-                               Planes3 rout, unsigned long long* rslot, ConvCheck check,
+                               Planes3 rout_d, unsigned long long* rslot, ConvCheck check,
                                FirstArgs fa, int sweeps, const Multi& mu, hipStream_t stream,
                                LaunchEvents ev) {
+  const PlanesOf<vec2_t<RT>> rout = as_r<RT>(rout_d);
   const int h = sweeps - 1, tx = RX - 2 * h, ty = RY - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
                                      : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
       block(RX * RY / 2);
   switch (sweeps) {
     case 1:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 0, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+      MB4_LAUNCH((k_stage_solve<RX, RY, 0, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
                  rslot, check, fa, mu);
     case 2:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 1, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+      MB4_LAUNCH((k_stage_solve<RX, RY, 1, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
                  rslot, check, fa, mu);
     case 3:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 2, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+      MB4_LAUNCH((k_stage_solve<RX, RY, 2, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
                  rslot, check, fa, mu);
     case 4:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 3, FIRST>), grid, block, ev, lat, phib_in, phib_out, rout,
+      MB4_LAUNCH((k_stage_solve<RX, RY, 3, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
                  rslot, check, fa, mu);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-template <int RX, int RY, bool F>
-hipError_t launch_iterate_region(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
-                                 Planes3 rout, int sweeps, unsigned long long* rnext,
-                                 ConvCheck check, ConvCheck fin, double2* u0_out,
-                                 const Multi& mu, hipStream_t stream, LaunchEvents ev) {
+template <int RX, int RY, bool F, class RT>
+hipError_t launch_iterate_region(const Lattice& lat, CPlanes3 Uin, Planes3 Uout,
+                                 CPlanes3 rbar_d, Planes3 rout_d, int sweeps,
+                                 unsigned long long* rnext, ConvCheck check, ConvCheck fin,
+                                 double2* u0_out, const Multi& mu, hipStream_t stream,
+                                 LaunchEvents ev) {
+  const CPlanesOf<vec2_t<RT>> rbar = as_r<RT>(rbar_d);
+  const PlanesOf<vec2_t<RT>> rout = as_r<RT>(rout_d);
   const int h = sweeps - 1, tx = RX - 2 - 2 * h, ty = RY - 2 - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
                                      : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
       block(RX * RY / 2);
   switch (sweeps) {
     case 1:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 0>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+      MB4_LAUNCH((k_iterate<RX, RY, F, 0, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
                  check, fin, u0_out, mu);
     case 2:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 1>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+      MB4_LAUNCH((k_iterate<RX, RY, F, 1, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
                  check, fin, u0_out, mu);
     case 3:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 2>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+      MB4_LAUNCH((k_iterate<RX, RY, F, 2, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
                  check, fin, u0_out, mu);
     case 4:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 3>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
+      MB4_LAUNCH((k_iterate<RX, RY, F, 3, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
                  check, fin, u0_out, mu);
     default:
       return hipErrorInvalidValue;
@@ -1141,27 +1220,32 @@ hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, i
                               unsigned long long* rslot, ConvCheck check, hipStream_t stream,
                               LaunchEvents ev) {
   const Planes3 none{{nullptr, nullptr, nullptr}};
-  return launch_solve_region<32, 32, false>(lat, phib, none, rout, rslot, check,
-                                            FirstArgs{nullptr, false}, sweeps, Multi{}, stream,
-                                            ev);
+  return launch_solve_region<32, 32, false, double>(lat, phib, none, rout, rslot, check,
+                                                    FirstArgs{nullptr, false}, sweeps, Multi{},
+                                                    stream, ev);
 }
 
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
                               Planes3 phib_out, hipStream_t stream, LaunchEvents ev,
-                              const Multi& mu, int region) {
+                              const Multi& mu, int region, bool fp32) {
   const CPlanes3 none{{nullptr, nullptr, nullptr}};
   const FirstArgs fa{u0max_slot, phib_out.s[0] != nullptr};
   const ConvCheck nochk{nullptr, 0, 0.0, false};
+  if (fp32) {
+    if (region != kRegion32x32 || fa.store_rhs) return hipErrorInvalidValue;
+    return launch_solve_region<32, 32, true, float>(lat, none, phib_out, rout, rslot, nochk, fa,
+                                                    sweeps, mu, stream, ev);
+  }
   switch (region) {
     case kRegion32x32:
-      return launch_solve_region<32, 32, true>(lat, none, phib_out, rout, rslot, nochk, fa,
+      return launch_solve_region<32, 32, true, double>(lat, none, phib_out, rout, rslot, nochk, fa,
                                                sweeps, mu, stream, ev);
     case kRegion64x16:
-      return launch_solve_region<64, 16, true>(lat, none, phib_out, rout, rslot, nochk, fa,
+      return launch_solve_region<64, 16, true, double>(lat, none, phib_out, rout, rslot, nochk, fa,
                                                sweeps, mu, stream, ev);
     case kRegion32x16:
-      return launch_solve_region<32, 16, true>(lat, none, phib_out, rout, rslot, nochk, fa,
+      return launch_solve_region<32, 16, true, double>(lat, none, phib_out, rout, rslot, nochk, fa,
                                                sweeps, mu, stream, ev);
     default:
       return hipErrorInvalidValue;
@@ -1178,18 +1262,22 @@ hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, P
 hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                           Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
                           ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
-                          LaunchEvents ev, const Multi& mu, int region) {
-#define MB4_ITER_REGION(RX, RY)                                                              \
-  return from_u0 ? launch_iterate_region<RX, RY, true>(lat, Uin, Uout, rbar, rout, sweeps,  \
-                                                       rnext, check, fin, u0_out, mu, stream, \
-                                                       ev)                                    \
-                 : launch_iterate_region<RX, RY, false>(lat, Uin, Uout, rbar, rout, sweeps, \
-                                                        rnext, check, fin, u0_out, mu,      \
-                                                        stream, ev)
+                          LaunchEvents ev, const Multi& mu, int region, bool fp32) {
+#define MB4_ITER_REGION(RX, RY, RT)                                                          \
+  return from_u0 ? launch_iterate_region<RX, RY, true, RT>(lat, Uin, Uout, rbar, rout,      \
+                                                           sweeps, rnext, check, fin,       \
+                                                           u0_out, mu, stream, ev)          \
+                 : launch_iterate_region<RX, RY, false, RT>(lat, Uin, Uout, rbar, rout,     \
+                                                            sweeps, rnext, check, fin,      \
+                                                            u0_out, mu, stream, ev)
+  if (fp32) {
+    if (region != kRegion32x32) return hipErrorInvalidValue;
+    MB4_ITER_REGION(32, 32, float);
+  }
   switch (region) {
-    case kRegion32x32: MB4_ITER_REGION(32, 32);
-    case kRegion64x16: MB4_ITER_REGION(64, 16);
-    case kRegion32x16: MB4_ITER_REGION(32, 16);
+    case kRegion32x32: MB4_ITER_REGION(32, 32, double);
+    case kRegion64x16: MB4_ITER_REGION(64, 16, double);
+    case kRegion32x16: MB4_ITER_REGION(32, 16, double);
     default: return hipErrorInvalidValue;
   }
 #undef MB4_ITER_REGION
@@ -1197,15 +1285,25 @@ hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlane
 
 hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
                                ConvCheck check, ConvCheck fin, double2* u0_out,
-                               hipStream_t stream, LaunchEvents ev, const Multi& mu) {
+                               hipStream_t stream, LaunchEvents ev, const Multi& mu, bool fp32) {
   const int n = lat.nx * lat.ny;
   const dim3 grid(mu.desc != nullptr ? mu.blocks : (n + kFinalSites - 1) / kFinalSites),
       block(kFinalSites);
+  if (fp32) {
+    const CPlanesOf<float2> rf = as_r<float>(rbar);
+    if (from_u0)
+      MB4_LAUNCH((k_final_update<true, float>), grid, block, ev, lat, Uin, rf, check, fin, u0_out,
+                 n, mu);
+    else
+      MB4_LAUNCH((k_final_update<false, float>), grid, block, ev, lat, Uin, rf, check, fin,
+                 u0_out, n, mu);
+  }
   if (from_u0)
-    MB4_LAUNCH(k_final_update<true>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n, mu);
+    MB4_LAUNCH((k_final_update<true, double>), grid, block, ev, lat, Uin, rbar, check, fin,
+               u0_out, n, mu);
   else
-    MB4_LAUNCH(k_final_update<false>, grid, block, ev, lat, Uin, rbar, check, fin, u0_out, n,
-               mu);
+    MB4_LAUNCH((k_final_update<false, double>), grid, block, ev, lat, Uin, rbar, check, fin,
+               u0_out, n, mu);
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

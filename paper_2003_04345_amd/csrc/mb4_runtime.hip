@@ -74,6 +74,7 @@ struct mb4_state {
   double t = 0, shift = 0, g = 0, h = 0;
   double eps = kDefaultEps;
   bool relative_eps = false;  // eps scaled by ||u_0||_inf
+  bool fp32 = false;          // FP32 inner stage solves
   int max_newton = kDefaultMaxNewton;
   int sweeps = kDefaultSweeps;
   hipStream_t stream = nullptr;
@@ -348,7 +349,8 @@ int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned 
     if (l == 1) {
       LAUNCH(s, kFirstSolve, step, 1,
              mb4::launch_first_solve(L, pp(r_planes(s, 1)), s->sweeps, rec + 1, rec,
-                                     Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_));
+                                     Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_,
+                                     mb4::Multi{}, mb4::kRegion32x32, s->fp32));
       continue;
     }
     const int j = l - 1;  // the iteration this pass updates
@@ -358,7 +360,7 @@ int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned 
     LAUNCH(s, kIterate, step, j,
            mb4::launch_iterate(L, uin, pp(u_planes(s, j)), cp(r_planes(s, j)),
                                pp(r_planes(s, l)), j == 1, s->sweeps, rec + l, chk, fin, s->u0,
-                               s->q, ev_));
+                               s->q, ev_, mb4::Multi{}, mb4::kRegion32x32, s->fp32));
   }
   const int j = last;
   const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
@@ -366,7 +368,7 @@ int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned 
   const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
   LAUNCH(s, kFinalEnd, step, j,
          mb4::launch_final_update(L, uin, cp(r_planes(s, j)), j == 1, chk, fin, s->u0, s->q,
-                                  ev_));
+                                  ev_, mb4::Multi{}, s->fp32));
   return MB4_OK;
 }
 
@@ -619,9 +621,12 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     if (opt->inner_sweeps > 0) o.inner_sweeps = opt->inner_sweeps;
     o.stream = opt->stream;
     o.mem_budget = opt->mem_budget;
-    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS)) != 0)
+    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS | MB4_FLAG_FP32_SOLVE)) != 0)
       return fail(MB4_EINVAL, "unknown bits in flags");
     o.flags = opt->flags;
+    if ((o.flags & MB4_FLAG_FP32_SOLVE) != 0 && o.inner_sweeps > mb4::kMaxFusedSweeps)
+      return fail(MB4_EINVAL, "FP32 inner solves take at most %d sweeps",
+                  mb4::kMaxFusedSweeps);
   }
   if (!all_finite(potential, size_t(sites)))
     return fail(MB4_EINVAL, "potential has non-finite entries");
@@ -646,6 +651,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   s->q = s->stream;
   s->use_graphs = (o.flags & MB4_FLAG_NO_GRAPHS) == 0;
   s->relative_eps = (o.flags & MB4_FLAG_RELATIVE_EPS) != 0;
+  s->fp32 = (o.flags & MB4_FLAG_FP32_SOLVE) != 0;
 
   int rc = MB4_OK;
   hipError_t e = hipGetDevice(&s->device);

@@ -116,7 +116,7 @@ def test_create_rejects_invalid_arguments(lib, kwargs):
 @pytest.mark.parametrize("field,value", [("eps", -1.0), ("eps", float("nan")), ("eps", 1.0),
                                          ("max_newton", -1), ("max_newton", 1001),
                                          ("inner_sweeps", -2), ("inner_sweeps", 65),
-                                         ("flags", 4), ("flags", 0x80000000)])
+                                         ("flags", 8), ("flags", 0x80000000)])
 def test_create_rejects_invalid_options(lib, field, value):
     opt = M.mb4_options_default()
     setattr(opt, field, value)
@@ -267,7 +267,7 @@ def test_ensemble_create_rejects_invalid_arguments(lib, case):
 
 
 @pytest.mark.parametrize("field,value", [("inner_sweeps", 5), ("eps", -1.0),
-                                         ("max_newton", 1001), ("flags", 4)])
+                                         ("max_newton", 1001), ("flags", 8)])
 def test_ensemble_create_rejects_invalid_options(lib, field, value):
     opt = M.mb4_options_default()
     setattr(opt, field, value)
@@ -294,3 +294,11 @@ def test_ensemble_calls_reject_null(lib):
     assert lib.mb4_ensemble_size(None) == -1
     assert lib.mb4_ensemble_region(None) == -1
     lib.mb4_ensemble_destroy(None)
+
+
+def test_fp32_solves_take_at_most_four_sweeps(lib):
+    opt = M.mb4_options_default()
+    opt.flags = M.MB4_FLAG_FP32_SOLVE
+    opt.inner_sweeps = 5
+    rc, out = _create(opt=opt)
+    assert rc == M.MB4_EINVAL and out.value is None

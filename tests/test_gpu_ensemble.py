@@ -163,3 +163,18 @@ def test_set_state_resets_member_counter_and_zero_state_is_fixed():
         p, q = ens.get_state(1)
         assert not p.any() and not q.any()
         assert ens.member_stats(0)["steps_done"] == 5
+
+
+def test_fp32_solve_members_match_single_states_bitwise():
+    torch_cuda()
+    inputs = _inputs(MEMBERS)
+    with _ensemble(MEMBERS, inputs, fp32_solve=True) as ens:
+        with pytest.raises(M.Mb4Error):
+            ens.set_region(M.MB4_REGION_64x16)
+        best, ms = ens.tune(2)
+        assert best == M.MB4_REGION_32x32 and ms[1] < 0 and ms[2] < 0
+        assert ens.step(25) == M.MB4_OK, M.error_detail()
+        got = [ens.get_state(i) for i in range(len(MEMBERS))]
+    for i, (m, (v, p, q)) in enumerate(zip(MEMBERS, inputs)):
+        (sp, sq), _, _ = _single(m, v, p, q, 25, fp32_solve=True)
+        assert np.array_equal(got[i][0], sp) and np.array_equal(got[i][1], sq), i

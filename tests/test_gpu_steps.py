@@ -213,3 +213,29 @@ def test_graph_replay_matches_eager_launches_bitwise():
             runs[graphs] = snaps
     for a, b in zip(runs[True], runs[False]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nx,ny", [(32, 32), (33, 17), (3, 3), (100, 65)])
+def test_fp32_inner_solves_match_oracle(nx, ny):
+    # MB4_FLAG_FP32_SOLVE: the stage solves run in FP32 inside the FP64
+    # Newton loop, which still converges to the FP64 root (error vs the
+    # FP64 oracle stated here: <= 1e-13 after 20 steps).
+    torch_cuda()
+    cfg = L.config("lattice32", nx=nx, ny=ny, sigma=min(3.0, nx / 3),
+                   defect_count=min(4, nx * ny // 4))
+    v, p, q = L.make_inputs(cfg)
+    gpu, h0, h1, stats = _run_gpu(cfg, 20, v, p, q, fp32_solve=True)
+    ref, _ = O.oracle_for(cfg, v, eps=EPS_PARITY).run(p + 1j * q, 20)
+    err = np.max(np.abs(gpu - ref))
+    print(f"fp32 solves {nx}x{ny}: 20 steps, max-abs vs FP64 oracle {err:.3e}")
+    assert err <= 1e-13
+    assert abs(h1 - h0) <= 1e-14 * abs(h0)
+
+
+def test_fp32_inner_solves_keep_the_iteration_count():
+    torch_cuda()
+    cfg = L.config("lattice2048", nx=512, ny=512, defect_count=262, sigma=16.0)
+    v, p, q = L.make_inputs(cfg)
+    _, _, _, s64 = _run_gpu(cfg, 10, v, p, q, eps=0.0)
+    _, _, _, s32 = _run_gpu(cfg, 10, v, p, q, eps=0.0, fp32_solve=True)
+    assert s32["newton_iters"] == s64["newton_iters"]
