@@ -205,6 +205,96 @@ def run_ensemble(args, torch, M) -> int:
     return 0
 
 
+def run_serving(args, torch, M) -> int:
+    """The serving mix: a Poisson trace of solve requests (200/s, sides 64 ..
+    1024, 100 .. 5000 steps, g in [0, 2]) submitted to mb4_server at their
+    arrival times and served with continuous batching and FP32 inner solves.
+    Latency runs from a request's scheduled arrival to its completion."""
+    trace = L.serving_trace(args.requests)
+    inputs = [L.make_inputs(prob) for _, prob in trace]
+    srv = M.MB4Server(int(args.arena_gib * (1 << 30)), max_active=args.max_active,
+                      batch_steps=args.batch_steps, eps=args.eps, inner_sweeps=args.sweeps,
+                      fp32_solve=True)
+    n = len(trace)
+    ids = [None] * n
+    done = set()
+    nxt = 0
+    polls = 0
+    torch.cuda.synchronize()
+    t0 = srv.clock()
+    while len(done) < n:
+        now = srv.clock() - t0
+        while nxt < n and trace[nxt][0] <= now:
+            v, p, q = inputs[nxt]
+            ids[nxt] = srv.submit(trace[nxt][1], v, p, q, trace[nxt][1].steps)
+            nxt += 1
+        queued, active = srv.poll()
+        polls += 1
+        for i in range(nxt):
+            if i not in done and srv.request(ids[i])["status"] in (M.MB4_REQ_DONE,
+                                                                   M.MB4_REQ_FAILED):
+                done.add(i)
+        if queued == 0 and active == 0 and nxt < n:
+            time.sleep(max(0.0, trace[nxt][0] - (srv.clock() - t0)))
+    infos = [srv.request(r) for r in ids]
+    failed = sum(1 for i in infos if i["status"] != M.MB4_REQ_DONE)
+    lat = np.array([i["t_done"] - (t0 + trace[k][0]) for k, i in enumerate(infos)])
+    makespan = max(i["t_done"] for i in infos) - t0
+    site_steps = sum(prob.nx * prob.ny * prob.steps for _, prob in trace)
+    drift = max(abs(i["energy_end"] - i["energy_start"]) / abs(i["energy_start"]) for i in infos)
+    # Error of the served results (FP32 inner solves) against the all-FP64
+    # path run alone, on the smallest requests, and against the oracle on
+    # the first 64 x 64 one (the FP64 path is itself checked against the
+    # oracle by the test suite).
+    small = sorted(range(n), key=lambda k: trace[k][1].nx * trace[k][1].steps)[:6]
+    err64 = []
+    for k in small:
+        prob = trace[k][1]
+        v, p, q = inputs[k]
+        gp, gq = srv.result(ids[k])
+        with M.MB4State(prob.nx, prob.ny, v, prob.g, prob.h) as st:
+            st.set_state(p, q)
+            st.step(prob.steps)
+            rp, rq = st.get_state()
+        err64.append(float(np.max(np.abs((gp - rp) + 1j * (gq - rq)))))
+    oracle_err = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        k = small[0]
+        prob = trace[k][1]
+        v, p, q = inputs[k]
+        gp, gq = srv.result(ids[k])
+        orc = O.oracle_for(prob, v, solver="direct" if prob.sites <= 64 * 64 else "gmres")
+        t_or = time.perf_counter()
+        ref, _ = orc.run(p + 1j * q, prob.steps)
+        t_or = time.perf_counter() - t_or
+        oracle_err = {"request": ids[k], "side": prob.nx, "steps": prob.steps,
+                      "max_abs": float(np.max(np.abs(gp + 1j * gq - ref)))}
+    stats = srv.stats()
+    srv.close()
+    result = {
+        "metric": METRIC, "value": site_steps / makespan, "unit": UNIT, "n_gpus": 1,
+        "steps": int(sum(prob.steps for _, prob in trace)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (f32 inner solves)",
+        "data": "synthetic (seeded requests: disorder, defects, wavepackets; Poisson arrivals)",
+        "config": {"workload": "serving", "requests": n, "rate_per_s": L.SERVING_RATE,
+                   "sides": list(L.SERVING_SIDES), "steps": list(L.SERVING_STEPS),
+                   "g": [0.0, 2.0], "h": 0.01, "arena_gib": args.arena_gib,
+                   "max_active": args.max_active, "batch_steps": args.batch_steps,
+                   "parallelism": "single GPU, continuous batching",
+                   "newton_eps": args.eps or 1e-13, "newton_test": "absolute (Algorithm 1)"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "makespan_s": makespan, "offered_site_steps": site_steps, "polls": polls,
+        "failed_requests": failed, "energy_drift": drift, "energy_drift_ok": drift <= 1e-14,
+        "error_vs_fp64_path": {"requests": len(err64), "max_abs": max(err64)},
+        "error_vs_oracle": oracle_err, "batches": stats["batches"],
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def cpu_baseline_member(sample_steps: int) -> dict:
     """The oracle as it stands, single-threaded, on realisation 0 of the
     ensemble for sample_steps steps."""
@@ -254,7 +344,15 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="lattice2048",
-                    choices=sorted(L.CONFIGS) + ["ensemble128"])
+                    choices=sorted(L.CONFIGS) + ["ensemble128", "serving"])
+    ap.add_argument("--requests", type=int, default=120,
+                    help="serving: requests in the Poisson trace")
+    ap.add_argument("--arena-gib", type=float, default=64.0,
+                    help="serving: device memory the server may use")
+    ap.add_argument("--max-active", type=int, default=256,
+                    help="serving: requests on the GPU at once")
+    ap.add_argument("--batch-steps", type=int, default=8,
+                    help="serving: steps per scheduling round")
     ap.add_argument("--members", type=int, default=L.ENSEMBLE_SIZE,
                     help="ensemble128: number of realisations")
     ap.add_argument("--tune-steps", type=int, default=32,
@@ -290,6 +388,8 @@ def main(argv=None) -> int:
         return 1
     if args.workload == "ensemble128":
         return run_ensemble(args, torch, M)
+    if args.workload == "serving":
+        return run_serving(args, torch, M)
     cfg = L.CONFIGS[args.workload]
     steps = args.steps if args.steps is not None else cfg.steps
     v, p, q = L.make_inputs(cfg)

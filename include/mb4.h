@@ -288,6 +288,80 @@ MB4_API int32_t mb4_ensemble_region(const mb4_ensemble* ens);
 MB4_API int mb4_ensemble_tune(mb4_ensemble* ens, int32_t steps, int32_t* best,
                               double* ms_per_step);
 
+/* ------------------------------------------------------------------------
+ * Serving: solve requests of different lattice sizes and step counts on one
+ * GPU with continuous batching.  Requests wait in a FIFO queue and are
+ * admitted as soon as an active slot and a contiguous range of the server's
+ * device arena are free (admission by HBM footprint).  Each mb4_server_poll
+ * runs one batch for all active requests together: every request advances
+ * min(batch_steps, remaining) steps in the same launches as the others, with
+ * its own Newton loop.  Finished requests are retired and their memory taken
+ * by the next ones.  A request's result is bit for bit what mb4_step gives
+ * it alone with the same options.  One host thread per server. */
+typedef struct mb4_server mb4_server;
+
+#define MB4_REQ_QUEUED 0
+#define MB4_REQ_ACTIVE 1
+#define MB4_REQ_DONE 2
+#define MB4_REQ_FAILED 3
+
+typedef struct {
+  int32_t status;              /* MB4_REQ_* */
+  int32_t nx, ny;
+  int64_t steps, steps_done;
+  double t_submit, t_admit, t_done; /* mb4_server_clock seconds; -1 if not yet */
+  double energy_start;         /* H at admission (mb4_energy convention) */
+  double energy_end;           /* H when retired */
+  int32_t last_newton_iters;   /* Newton iterations of the last accepted step */
+  int32_t error;               /* MB4_ENOCONV for a failed request, else 0 */
+} mb4_request_info;
+
+typedef struct {
+  int64_t capacity_sites, used_sites;
+  int32_t queued, active;
+  int64_t batches;
+  double site_steps;           /* lattice-site-steps completed */
+} mb4_server_info;
+
+/* Creates a server on the current device whose device memory stays within
+ * arena_bytes (member fields: 216 bytes per site, 168 with
+ * MB4_FLAG_FP32_SOLVE, plus step records).  max_active (1 .. 65536) bounds
+ * the requests on the GPU at once, batch_steps (1 .. 32) the steps per poll.
+ * opt as for mb4_ensemble_create (inner_sweeps <= 4; mem_budget ignored).
+ * Errors: MB4_EINVAL, MB4_ENOMEM, MB4_EDEVICE. */
+MB4_API int mb4_server_create(uint64_t arena_bytes, int32_t max_active, int32_t batch_steps,
+                              const mb4_options* opt, mb4_server** out);
+MB4_API void mb4_server_destroy(mb4_server* srv);
+
+/* Seconds since the server was created (the clock of mb4_request_info). */
+MB4_API double mb4_server_clock(const mb4_server* srv);
+
+/* Queues a request: lattice, potential (nx*ny), nonlinearity and h as for
+ * mb4_create, initial psi = p + i q (nx*ny each), and steps >= 0 MB4 steps.
+ * All inputs are copied.  *id receives the request id.  MB4_EINVAL if the
+ * request could never fit the arena. */
+MB4_API int mb4_server_submit(mb4_server* srv, const mb4_lattice* lattice,
+                              const double* potential, const mb4_nonlinearity* nonlinearity,
+                              double h, const double* p, const double* q, int64_t steps,
+                              int64_t* id);
+
+/* One scheduling round: admit what fits, run one batch, retire what is
+ * done.  queued / active (may be NULL) receive the counts afterwards.  A
+ * request whose Newton loop fails is retired as MB4_REQ_FAILED; the others go
+ * on. */
+MB4_API int mb4_server_poll(mb4_server* srv, int32_t* queued, int32_t* active);
+
+MB4_API int mb4_server_request(mb4_server* srv, int64_t id, mb4_request_info* info);
+
+/* psi of a finished request (the last accepted step of a failed one) into
+ * host arrays of nx*ny doubles. */
+MB4_API int mb4_server_result(mb4_server* srv, int64_t id, double* p, double* q);
+
+/* Forgets a finished request. */
+MB4_API int mb4_server_release(mb4_server* srv, int64_t id);
+
+MB4_API int mb4_server_stats(const mb4_server* srv, mb4_server_info* stats);
+
 /* Static description of a status code. */
 MB4_API const char* mb4_strerror(int code);
 

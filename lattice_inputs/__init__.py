@@ -184,6 +184,39 @@ def ensemble(size: int = ENSEMBLE_SIZE) -> list[LatticeProblem]:
     return [ensemble_member(r) for r in range(size)]
 
 
+# The serving mix: solve requests arriving as a Poisson process, each with
+# its own lattice side, step count, nonlinearity and disorder realisation.
+SERVING_SIDES = (64, 128, 256, 512, 1024)
+SERVING_RATE = 200.0          # mean arrivals per second
+SERVING_STEPS = (100, 5000)   # uniform, inclusive
+SERVING_TRACE_SEED = 7000
+
+
+def serving_request(rid: int) -> LatticeProblem:
+    """Request rid of the serving mix (its disorder seed is rid): side drawn
+    uniformly from SERVING_SIDES, steps uniform in SERVING_STEPS, g uniform in
+    [0, 2]; W = 1 disorder with 0.5% defects at +50, sigma 8 (32 for the
+    largest side), k = (pi/4, 0), h = 0.01."""
+    u = draw_uniform(rid, 10, 3)
+    side = SERVING_SIDES[min(int(u[0] * len(SERVING_SIDES)), len(SERVING_SIDES) - 1)]
+    lo, hi = SERVING_STEPS
+    steps = lo + min(int(u[1] * (hi - lo + 1)), hi - lo)
+    return LatticeProblem(
+        name=f"serving_r{rid}", nx=side, ny=side, disorder_w=1.0,
+        defect_count=_defects(0.005, side * side), defect_v=50.0, g=2.0 * float(u[2]),
+        sigma=32.0 if side >= 1024 else 8.0, kx=math.pi / 4, ky=0.0, h=0.01, steps=steps,
+        seed=rid)
+
+
+def serving_trace(n: int, rate: float = SERVING_RATE,
+                  seed: int = SERVING_TRACE_SEED) -> list[tuple[float, LatticeProblem]]:
+    """n requests (ids 1 .. n) with Poisson arrival times at `rate` per
+    second: exponential gaps -ln(1 - u) / rate from the seeded generator."""
+    u = draw_uniform(seed, 11, n)
+    t = np.cumsum(-np.log1p(-u) / rate)
+    return [(float(t[i]), serving_request(i + 1)) for i in range(n)]
+
+
 def config(name: str, **overrides) -> LatticeProblem:
     """A copy of a named workload with some fields replaced."""
     base = CONFIGS[name].as_dict()

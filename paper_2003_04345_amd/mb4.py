@@ -47,6 +47,24 @@ MB4_REGION_COUNT = 3
 REGION_NAMES = ("32x32", "64x16", "32x16")
 
 
+MB4_REQ_QUEUED = 0
+MB4_REQ_ACTIVE = 1
+MB4_REQ_DONE = 2
+MB4_REQ_FAILED = 3
+
+
+class mb4_request_info(Structure):
+    _fields_ = [("status", c_int32), ("nx", c_int32), ("ny", c_int32), ("steps", c_int64),
+                ("steps_done", c_int64), ("t_submit", c_double), ("t_admit", c_double),
+                ("t_done", c_double), ("energy_start", c_double), ("energy_end", c_double),
+                ("last_newton_iters", c_int32), ("error", c_int32)]
+
+
+class mb4_server_info(Structure):
+    _fields_ = [("capacity_sites", c_int64), ("used_sites", c_int64), ("queued", c_int32),
+                ("active", c_int32), ("batches", c_int64), ("site_steps", c_double)]
+
+
 class Mb4Error(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         self.code = code
@@ -90,6 +108,18 @@ _SIGNATURES = {
     "mb4_ensemble_set_region": (c_int, [c_void_p, c_int32]),
     "mb4_ensemble_region": (c_int32, [c_void_p]),
     "mb4_ensemble_tune": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_double)]),
+    "mb4_server_create": (c_int, [c_uint64, c_int32, c_int32, POINTER(mb4_options),
+                                  POINTER(c_void_p)]),
+    "mb4_server_destroy": (None, [c_void_p]),
+    "mb4_server_clock": (c_double, [c_void_p]),
+    "mb4_server_submit": (c_int, [c_void_p, POINTER(mb4_lattice), POINTER(c_double),
+                                  POINTER(mb4_nonlinearity), c_double, POINTER(c_double),
+                                  POINTER(c_double), c_int64, POINTER(c_int64)]),
+    "mb4_server_poll": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "mb4_server_request": (c_int, [c_void_p, c_int64, POINTER(mb4_request_info)]),
+    "mb4_server_result": (c_int, [c_void_p, c_int64, POINTER(c_double), POINTER(c_double)]),
+    "mb4_server_release": (c_int, [c_void_p, c_int64]),
+    "mb4_server_stats": (c_int, [c_void_p, POINTER(mb4_server_info)]),
     "mb4_strerror": (c_char_p, [c_int]),
     "mb4_error_detail": (c_char_p, []),
 }
@@ -463,6 +493,106 @@ class MB4Ensemble:
         if getattr(self, "_e", None) is not None:
             load_library().mb4_ensemble_destroy(self._e)
             self._e = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Serving (mb4_server_*).
+
+class MB4Server:
+    """Owning wrapper of one mb4_server: a request loop with continuous
+    batching.  submit() queues a request, poll() runs one scheduling round
+    (admission, one batch of steps for every active request, retirement)."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 256, batch_steps: int = 8,
+                 eps: float = 0.0, max_newton: int = 0, inner_sweeps: int = 0,
+                 fp32_solve: bool = False, relative_eps: bool = False,
+                 stream: int | None = None):
+        opt = mb4_options_default()
+        if eps:
+            opt.eps = eps
+        if max_newton:
+            opt.max_newton = max_newton
+        if inner_sweeps:
+            opt.inner_sweeps = inner_sweeps
+        opt.stream = stream
+        opt.flags = ((MB4_FLAG_FP32_SOLVE if fp32_solve else 0) |
+                     (MB4_FLAG_RELATIVE_EPS if relative_eps else 0))
+        out = c_void_p()
+        _check(load_library().mb4_server_create(int(arena_bytes), int(max_active),
+                                                int(batch_steps), byref(opt), byref(out)),
+               "mb4_server_create")
+        self._s = out.value
+        self._shape = {}
+
+    def clock(self) -> float:
+        return load_library().mb4_server_clock(self._s)
+
+    def submit(self, problem, potential, p, q, steps: int) -> int:
+        """problem: object with nx, ny, g, h (t_hop, diag_shift optional)."""
+        nx, ny = int(problem.nx), int(problem.ny)
+        n = nx * ny
+        lat = mb4_lattice(nx, ny, float(getattr(problem, "t_hop", 1.0)),
+                          float(getattr(problem, "diag_shift", 0.0)))
+        v = _host(potential, n)
+        pp = _host(p, n)
+        qq = _host(q, n)
+        rid = c_int64()
+        _check(load_library().mb4_server_submit(
+            self._s, byref(lat), v.ctypes.data_as(POINTER(c_double)),
+            byref(mb4_nonlinearity(float(problem.g))), float(problem.h),
+            pp.ctypes.data_as(POINTER(c_double)), qq.ctypes.data_as(POINTER(c_double)),
+            int(steps), byref(rid)), "mb4_server_submit")
+        self._shape[rid.value] = n
+        return rid.value
+
+    def poll(self) -> tuple[int, int]:
+        queued = c_int32()
+        active = c_int32()
+        _check(load_library().mb4_server_poll(self._s, byref(queued), byref(active)),
+               "mb4_server_poll")
+        return queued.value, active.value
+
+    def request(self, rid: int) -> dict:
+        info = mb4_request_info()
+        _check(load_library().mb4_server_request(self._s, int(rid), byref(info)),
+               "mb4_server_request")
+        return {name: getattr(info, name) for name, _ in mb4_request_info._fields_}
+
+    def result(self, rid: int) -> tuple[np.ndarray, np.ndarray]:
+        n = self._shape[rid]
+        p = np.empty(n)
+        q = np.empty(n)
+        _check(load_library().mb4_server_result(self._s, int(rid),
+                                                p.ctypes.data_as(POINTER(c_double)),
+                                                q.ctypes.data_as(POINTER(c_double))),
+               "mb4_server_result")
+        return p, q
+
+    def release(self, rid: int) -> None:
+        _check(load_library().mb4_server_release(self._s, int(rid)), "mb4_server_release")
+        self._shape.pop(rid, None)
+
+    def stats(self) -> dict:
+        info = mb4_server_info()
+        _check(load_library().mb4_server_stats(self._s, byref(info)), "mb4_server_stats")
+        return {name: getattr(info, name) for name, _ in mb4_server_info._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_s", None) is not None:
+            load_library().mb4_server_destroy(self._s)
+            self._s = None
 
     def __enter__(self):
         return self

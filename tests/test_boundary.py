@@ -302,3 +302,68 @@ def test_fp32_solves_take_at_most_four_sweeps(lib):
     opt.inner_sweeps = 5
     rc, out = _create(opt=opt)
     assert rc == M.MB4_EINVAL and out.value is None
+
+
+def test_server_struct_layouts_match_binding():
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "mb4.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mb4_request_info),
+         offsetof(mb4_request_info, steps), offsetof(mb4_request_info, steps_done),
+         offsetof(mb4_request_info, t_submit), offsetof(mb4_request_info, energy_start),
+         offsetof(mb4_request_info, energy_end), offsetof(mb4_request_info, last_newton_iters),
+         offsetof(mb4_request_info, error));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(mb4_server_info), offsetof(mb4_server_info, queued),
+         offsetof(mb4_server_info, active), offsetof(mb4_server_info, batches),
+         offsetof(mb4_server_info, site_steps));
+  return 0;
+}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "layout")
+        res = subprocess.run(["gcc", "-std=c99", f"-I{os.path.dirname(HEADER)}", "-x", "c", "-",
+                              "-o", exe], input=prog, capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    a = [int(x) for x in lines[0].split()]
+    b = [int(x) for x in lines[1].split()]
+    R, S = M.mb4_request_info, M.mb4_server_info
+    assert a == [ctypes.sizeof(R), R.steps.offset, R.steps_done.offset, R.t_submit.offset,
+                 R.energy_start.offset, R.energy_end.offset, R.last_newton_iters.offset,
+                 R.error.offset]
+    assert b == [ctypes.sizeof(S), S.queued.offset, S.active.offset, S.batches.offset,
+                 S.site_steps.offset]
+
+
+@pytest.mark.parametrize("arena,max_active,batch,field,value", [
+    (1 << 30, 0, 8, None, None),
+    (1 << 30, 65537, 8, None, None),
+    (1 << 30, 16, 0, None, None),
+    (1 << 30, 16, 33, None, None),
+    (1 << 20, 16, 8, None, None),           # arena too small for anything
+    (1 << 30, 16, 8, "inner_sweeps", 5),
+    (1 << 30, 16, 8, "flags", 8),
+    (1 << 30, 16, 8, "eps", float("nan")),
+])
+def test_server_create_rejects_invalid_arguments(lib, arena, max_active, batch, field, value):
+    opt = M.mb4_options_default()
+    if field is not None:
+        setattr(opt, field, value)
+    out = ctypes.c_void_p(1234)
+    rc = lib.mb4_server_create(arena, max_active, batch, ctypes.byref(opt), ctypes.byref(out))
+    assert rc == M.MB4_EINVAL
+    assert out.value is None
+
+
+def test_server_calls_reject_null(lib):
+    assert lib.mb4_server_poll(None, None, None) == M.MB4_EINVAL
+    assert lib.mb4_server_submit(None, None, None, None, 0.01, None, None, 1, None) == M.MB4_EINVAL
+    assert lib.mb4_server_request(None, 1, None) == M.MB4_EINVAL
+    assert lib.mb4_server_result(None, 1, None, None) == M.MB4_EINVAL
+    assert lib.mb4_server_release(None, 1) == M.MB4_EINVAL
+    assert lib.mb4_server_stats(None, None) == M.MB4_EINVAL
+    assert lib.mb4_server_clock(None) == -1.0
+    lib.mb4_server_destroy(None)
