@@ -47,6 +47,9 @@ HBM_PEAK_GBS = 8000.0
 #                          iteration 1 from U = u0, residual and the next
 #                          stage solve, Phibar kept on chip)
 #   iterate:               u0 16 + V 8 + U 48 + rbar 48 -> U 48 + rbar 48
+#   final_first:           U_3 16 + rbar 48 + V 8 -> u0 16 + rbar 48 (the final
+#                          update of a step fused with the next step's first
+#                          stage solve, which builds u_0 on its region itself)
 BYTES_PER_SITE = {
     "stage_solve_first": 72,
     "stage_solve": 120,
@@ -56,17 +59,20 @@ BYTES_PER_SITE = {
     "final_update": 80,
     "iterate_first": 168,
     "iterate": 216,
+    "final_first": 136,
 }
 # With FP32 inner solves the stage corrections rbar are 24 B/site instead of 48:
 #   stage_solve_first: u0 16 + V 8 -> rbar 24
 #   iterate_first:     u0 16 + V 8 + rbar 24 -> U 48 + rbar 24
 #   iterate:           u0 16 + V 8 + U 48 + rbar 24 -> U 48 + rbar 24
 #   final_update:      U_3 16 + rbar 24 -> u0 16
+#   final_first:       U_3 16 + rbar 24 + V 8 -> u0 16 + rbar 24
 BYTES_PER_SITE_FP32 = {
     "stage_solve_first": 48,
     "iterate_first": 120,
     "iterate": 168,
     "final_update": 56,
+    "final_first": 88,
 }
 
 
@@ -130,10 +136,15 @@ def cpu_baseline(sample_side: int, sample_steps: int, workload: str) -> dict:
 
 def step_bytes_per_site(iters: int, fp32_solve: bool = False) -> int:
     """Algorithmic HBM bytes per site of one whole step with `iters` Newton
-    iterations: first solve, fused iterations, final update."""
+    iterations inside a batch: final update fused with the first solve, then
+    the fused iterations."""
     b = BYTES_PER_SITE_FP32 if fp32_solve else BYTES_PER_SITE
-    return (b["stage_solve_first"] + b["iterate_first"] * (iters >= 2) +
-            b["iterate"] * max(iters - 2, 0) + b["final_update"])
+    if iters < 2:
+        return b["stage_solve_first"] + b["final_update"]
+    # In a batch the final update of each step is fused into the next first
+    # solve (the first step's plain first solve and the last step's final
+    # update are not counted).
+    return b["final_first"] + b["iterate_first"] + b["iterate"] * (iters - 2)
 
 
 def run_ensemble(args, torch, M) -> int:

@@ -182,45 +182,65 @@ Lattice lattice_of(const Engine* e) {
 Planes3 pp(double2* const* a) { return Planes3{{a[0], a[1], a[2]}}; }
 CPlanes3 cp(double2* const* a) { return CPlanes3{{a[0], a[1], a[2]}}; }
 double2* const* u_planes(const Engine* e, int j) { return (j % 2 == 1) ? e->Ua : e->Ub; }
-double2* const* r_planes(const Engine* e, int l) { return (l % 2 == 1) ? e->ra : e->rb; }
+double2* const* r_planes(const Engine* e, int l) { return (l & 1) ? e->ra : e->rb; }
 
 ConvCheck conv_check(const Engine* e, const unsigned long long* rec, int prev) {
   return ConvCheck{rec, prev, e->cfg.eps, e->cfg.relative_eps};
 }
 
-// Step `step` of the batch, Newton iterations 1 .. iters, every member.
-int enqueue_step(Engine* e, int step, int iters) {
+// Step `step` of a batch of `count` steps, Newton iterations 1 .. iters, every
+// member.  With iters >= 2 the final update of step k - 1 is fused into the
+// first solve of step k, only the last step of the batch has its own final
+// update, and the stage-correction buffers alternate with sigma = k * iters
+// (so the first solve of step k does not write what that final update reads).
+int enqueue_step(Engine* e, int step, int count, int iters) {
   const Lattice L = lattice_of(e);
-  const int count = int(e->desc.size());
-  unsigned long long* rec = e->ring + size_t(step) * count * e->rec_len;
+  const int members = int(e->desc.size());
+  unsigned long long* rec = e->ring + size_t(step) * members * e->rec_len;
   const Multi mf = multi_of(e, kFirst, step), mi = multi_of(e, kIter, step),
               mfin = multi_of(e, kFinal, step);
   const bool f32 = e->cfg.fp32;
-  HIP_TRY(launch_first_solve(L, pp(r_planes(e, 1)), e->cfg.sweeps, rec + 1, rec,
-                             Planes3{{nullptr, nullptr, nullptr}}, e->q, {}, mf, e->region,
-                             f32));
+  const bool fuse = iters >= 2;
+  const int sigma = fuse ? (step * iters) & 1 : 0;
+  auto rp = [&](int l) { return r_planes(e, l + sigma); };
+  if (fuse && step > 0) {
+    const unsigned long long* prev = rec - size_t(members) * e->rec_len;
+    const int sigma_prev = (sigma + iters) & 1;
+    const PrevStep pv{cp(u_planes(e, iters - 1)), cp(r_planes(e, iters + sigma_prev)),
+                      conv_check(e, prev, iters - 1), conv_check(e, prev, iters), e->u0};
+    HIP_TRY(launch_first_solve(L, pp(rp(1)), e->cfg.sweeps, rec + 1,
+                               e->cfg.relative_eps ? rec : nullptr,
+                               Planes3{{nullptr, nullptr, nullptr}}, e->q, {}, mf, e->region,
+                               f32, &pv));
+  } else {
+    HIP_TRY(launch_first_solve(L, pp(rp(1)), e->cfg.sweeps, rec + 1,
+                               e->cfg.relative_eps ? rec : nullptr,
+                               Planes3{{nullptr, nullptr, nullptr}}, e->q, {}, mf, e->region,
+                               f32));
+  }
   for (int l = 2; l <= iters; ++l) {
     const int j = l - 1;
     const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
     const ConvCheck fin = conv_check(e, rec, j);
     const CPlanes3 uin = j >= 2 ? cp(u_planes(e, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
-    HIP_TRY(launch_iterate(L, uin, pp(u_planes(e, j)), cp(r_planes(e, j)), pp(r_planes(e, l)),
-                           j == 1, e->cfg.sweeps, rec + l, chk, fin, e->u0, e->q, {}, mi,
-                           e->region, f32));
+    HIP_TRY(launch_iterate(L, uin, pp(u_planes(e, j)), cp(rp(j)), pp(rp(l)), j == 1,
+                           e->cfg.sweeps, rec + l, chk, fin, e->u0, e->q, {}, mi, e->region,
+                           f32));
   }
+  if (fuse && step + 1 < count) return MB4_OK;  // step + 1 takes the final update
   const int j = iters;
   const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
   const ConvCheck fin = conv_check(e, rec, j);
   const CPlanes3 uin = j >= 2 ? cp(u_planes(e, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
-  HIP_TRY(launch_final_update(L, uin, cp(r_planes(e, j)), j == 1, chk, fin, e->u0, e->q, {},
-                              mfin, f32));
+  HIP_TRY(launch_final_update(L, uin, cp(rp(j)), j == 1, chk, fin, e->u0, e->q, {}, mfin,
+                              f32));
   return MB4_OK;
 }
 
 int enqueue_batch(Engine* e, int count, int iters) {
   HIP_TRY(launch_clear(e->ring, count * int(e->desc.size()) * e->rec_len, e->q));
   for (int k = 0; k < count; ++k) {
-    const int rc = enqueue_step(e, k, iters);
+    const int rc = enqueue_step(e, k, count, iters);
     if (rc != MB4_OK) return rc;
   }
   return MB4_OK;

@@ -106,16 +106,33 @@ hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 // quadrature, the update U + (T (x) I) rbar and the norms stay FP64.  Only
 // the 32 x 32 region exists in this precision.
 
+// The final update of the previous step, fused into the first solve of the
+// next: if that step converged at its last iteration (`fin` holds, `chk`
+// does not), the region's u_0 is u_1 = U[2] + (T rbar)_3 and each block
+// writes it over u0_out for its tile; otherwise u_0 is read as it is (the
+// step converged earlier and an update pass wrote u_1, or it did not converge
+// and u_0 kept its value).  U[2] must be U_3 of an iteration >= 1 (a step of
+// one iteration has base u_0, which the blocks overwrite, so it is not
+// fused), and rbar must not be the plane set the first solve writes.  With a
+// Multi, the records are member 0's and a member whose previous step was its
+// last in the batch gets only its final update.
+struct PrevStep {
+  CPlanes3 U;
+  CPlanes3 rbar;  // float2 planes with fp32
+  ConvCheck chk, fin;
+  double2* u0_out;
+};
+
 // Newton iteration 1, stage solve: `sweeps` (1..4) block-Jacobi sweeps of
 // (I - h lambda_i J) r_i = -Phibar_i with Phibar_i = -h TC_i f(u_0) (the
 // residual at U^0 = e_3 (x) u_0) built in place, into rout.  Records
-// ||u_0||_inf in *u0max_slot and ||(T (x) I) r||_inf in *rslot (if not NULL),
+// ||u_0||_inf in *u0max_slot and ||(T (x) I) r||_inf in *rslot (each if not NULL),
 // and writes that Phibar to phib_out when phib_out.s[0] is not NULL.
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
                               Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {},
                               const Multi& mu = {}, int region = kRegion32x32,
-                              bool fp32 = false);
+                              bool fp32 = false, const PrevStep* prev = nullptr);
 
 // Newton iteration l >= 2 (or a kernel-level call), stage solve: `sweeps`
 // (1..4) block-Jacobi sweeps from r = 0 for the three stage systems

@@ -48,6 +48,14 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return v;
 }
 
+// The same for v in [-n, 2n) (a region on a lattice at least as wide as the
+// region), without loops; `fast` (uniform) says whether that holds.
+__device__ __forceinline__ int wrap_in(int v, int n, bool fast) {
+  if (!fast) return wrap(v, n);
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that XCD
 // k receives the k-th contiguous range of logical tiles.
 __device__ __forceinline__ int xcd_block(int b, int nb) {
@@ -88,6 +96,21 @@ __device__ __forceinline__ unsigned long long umax(unsigned long long a, unsigne
   return a > b ? a : b;
 }
 
+// Running max of |x| that keeps non-finite values.  The max is a plain FP64
+// max, which skips a NaN, so the sum of the same values (NaN if any was) rides
+// along; bits() is the IEEE pattern of the max, or of a NaN, which sorts
+// above +inf in the unsigned block and device maxima.
+struct NormAcc {
+  double m = 0.0, s = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    m = fmax(m, fabs(x));
+    s += x;
+  }
+  __device__ __forceinline__ unsigned long long bits() const {
+    return s != s ? 0x7ff8000000000000ull : abs_bits(m);
+  }
+};
+
 __device__ __forceinline__ double bits_double(unsigned long long b) {
   return __longlong_as_double(static_cast<long long>(b));
 }
@@ -108,13 +131,13 @@ __device__ __forceinline__ bool converged_at(const ConvCheck& c) {
 // index within the member, and `base` / `rec` are the member's site and
 // record offsets.  `skip`: the member takes no more steps in this batch.
 struct Loc {
-  int b;
+  int b, m;
   long long base, rec;
   bool skip;
 };
 
 __device__ __forceinline__ Loc locate(const Multi& mu, Lattice& L, int b) {
-  Loc w{b, 0, 0, false};
+  Loc w{b, 0, 0, 0, false};
   if (mu.desc == nullptr) return w;
   int lo = 0, hi = mu.count - 1;
   while (lo < hi) {
@@ -124,6 +147,7 @@ __device__ __forceinline__ Loc locate(const Multi& mu, Lattice& L, int b) {
   }
   const MemberDesc d = mu.desc[lo];
   w.b = b - mu.block0[lo];
+  w.m = lo;
   w.base = d.base;
   w.rec = static_cast<long long>(lo) * mu.rec_stride;
   w.skip = mu.todo != nullptr && mu.step >= mu.todo[lo];
@@ -429,10 +453,31 @@ __device__ __forceinline__ vec2_t<T> block_solve_t(const SiteBlockT<T>& s, T hl,
                  inv * ((T(1) - hl * s.a) * bq - hl * s.cc * bp));
 }
 
-// 1 / det(I - hl J_site) in precision T.
+// 1 / det(I - h lambda_i J_site) for the three stages, d_i = 1 +
+// (h lambda_i)^2 (bb cc - a^2).  In FP64 one division serves all three:
+// inv_0 = d_1 d_2 / (d_0 d_1 d_2) and so on (a few ulp; the product of the
+// d_i overflows only for potentials beyond 1e100).  FP32 divides per stage,
+// where that product could overflow for large potentials.
 template <class T>
-__device__ __forceinline__ T block_inv(const SiteBlockT<T>& s, T hl) {
-  return T(1) / (T(1) + hl * hl * (s.bb * s.cc - s.a * s.a));
+__device__ __forceinline__ void block_invs(const SiteBlockT<T>& s, double h, T (&inv)[3]) {
+  const T dd = s.bb * s.cc - s.a * s.a;
+  T d[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T hl = T(h * MB4_LAMBDA[i]);
+    d[i] = T(1) + hl * hl * dd;
+  }
+  if (sizeof(T) == sizeof(double)) {
+    const T d01 = d[0] * d[1];
+    const T r = T(1) / (d01 * d[2]);
+    const T t = d[2] * r;
+    inv[0] = d[1] * t;
+    inv[1] = d[0] * t;
+    inv[2] = d01 * r;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) inv[i] = T(1) / d[i];
+  }
 }
 
 // f(u_0) = S grad H = (A q + g n q, -(A p + g n p)) at one site, from u and
@@ -473,17 +518,33 @@ struct FirstArgs {
   bool store_rhs;                  // also write Phibar of the tile
 };
 
-template <int RX, int RY, int H, bool FIRST, class RT>
+template <int RX, int RY, int H, bool FIRST, class RT, bool PREV>
 __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
                                                               Planes3 phib_out,
                                                               PlanesOf<vec2_t<RT>> rout,
                                                               unsigned long long* rslot,
                                                               ConvCheck chk, FirstArgs fa,
-                                                              Multi mu) {
+                                                              Multi mu, PrevStep pv) {
   using R2 = vec2_t<RT>;
   constexpr int kSolveThreads = RX * RY / 2;
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
-  if (w.skip) return;
+  // PREV: the final update of the previous step, if it converged at its last
+  // iteration (see PrevStep).
+  bool apply = false;
+  CPlanesOf<R2> prb{};
+  if (PREV) {
+    if (mu.todo != nullptr && mu.step - 1 >= mu.todo[w.m]) return;
+    offset_check(pv.chk, w.rec);
+    offset_check(pv.fin, w.rec);
+    apply = !converged_at(pv.chk) && converged_at(pv.fin);
+    offset_planes(pv.U, w.base);
+    pv.u0_out = offset_ptr(pv.u0_out, w.base);
+    // rbar has element type R2: reinterpret first, then offset by sites.
+#pragma unroll
+    for (int i = 0; i < 3; ++i) prb.s[i] = reinterpret_cast<const R2*>(pv.rbar.s[i]);
+    offset_planes(prb, w.base);
+  }
+  if (w.skip && !(PREV && apply)) return;
   offset_check(chk, w.rec);
   if (converged_at(chk)) return;
   offset_planes(phib_in, w.base);
@@ -496,13 +557,40 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
   constexpr int PER = RN / kSolveThreads;
   static_assert(RN % kSolveThreads == 0, "region must be a whole number of passes");
   constexpr int UX = RX + 2, UN = FIRST ? UX * (RY + 2) : 1;
+  // u_0 on the region plus a one-site ring (FIRST) shares the LDS of the
+  // stage iterates: it is dead once the right-hand sides are formed.
   __shared__ R2 sr[3][RN];
-  __shared__ double2 su[UN];
+  static_assert(UN * sizeof(double2) <= sizeof(sr), "u_0 staging must fit the iterate buffer");
+  double2* const su = reinterpret_cast<double2*>(&sr[0][0]);
   const int nx = L.nx, ny = L.ny;
   int tx0, ty0;
   strip_tile(w.b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
   tx0 *= TSX;
   ty0 *= TSY;
+  const bool fast = nx >= RX + 2 && ny >= RY + 2;
+  // u_1 of the previous step at one site.
+  auto u_new = [&](int site) {
+    double2 r[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) r[m] = to_d2(prb.s[m][site]);
+    const double2 base = pv.U.s[2][site];
+    const double2 d = t_apply(2, r);
+    return make_double2(base.x + d.x, base.y + d.y);
+  };
+  if (PREV && w.skip) {
+    // The member took its last step of the batch: only its final update.
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = threadIdx.x + j * kSolveThreads;
+      const int lx = idx % RX, ly = idx / RX;
+      if (lx >= H && lx < H + TSX && ly >= H && ly < H + TSY && tx0 + lx - H < nx &&
+          ty0 + ly - H < ny) {
+        const int site = (ty0 + ly - H) * nx + (tx0 + lx - H);
+        pv.u0_out[site] = u_new(site);
+      }
+    }
+    return;
+  }
 
   // Own positions first: their potential is loaded before the u_0 staging
   // below, so both sets of loads are in flight together.
@@ -512,13 +600,15 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kSolveThreads;
     const int lx = idx % RX, ly = idx / RX;
-    gsite[j] = wrap(ty0 - H + ly, ny) * nx + wrap(tx0 - H + lx, nx);
+    gsite[j] = wrap_in(ty0 - H + ly, ny, fast) * nx + wrap_in(tx0 - H + lx, nx, fast);
     vv[j] = L.V[gsite[j]];
   }
   if (FIRST) {
     for (int e = threadIdx.x; e < UN; e += kSolveThreads) {
       const int ex = e % UX, ey = e / UX;
-      su[e] = L.u0[wrap(ty0 - H - 1 + ey, ny) * nx + wrap(tx0 - H - 1 + ex, nx)];
+      const int site =
+          wrap_in(ty0 - H - 1 + ey, ny, fast) * nx + wrap_in(tx0 - H - 1 + ex, nx, fast);
+      su[e] = (PREV && apply) ? u_new(site) : L.u0[site];
     }
     __syncthreads();
   }
@@ -526,7 +616,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
   R2 rhs[PER][3];
   SiteBlockT<RT> blk[PER];
   RT inv[PER][3];
-  unsigned long long um = 0ull;
+  NormAcc um;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kSolveThreads;
@@ -536,16 +626,20 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
     const double2 u = FIRST ? su[e] : L.u0[site];
     const double v = vv[j];
     blk[j] = block_in<RT>(site_block(L, u, v));
+    block_invs(blk[j], L.h, inv[j]);
     double2 f = make_double2(0.0, 0.0);
     if (FIRST) {
       f = f_from(L, u, v, su[e - 1], su[e + 1], su[e - UX], su[e + UX]);
       const bool out = lx >= H && lx < H + TSX && ly >= H && ly < H + TSY &&
                        tx0 + lx - H < nx && ty0 + ly - H < ny;
-      if (out) um = umax(um, umax(abs_bits(u.x), abs_bits(u.y)));
+      if (out) {
+        um.add(u.x);
+        um.add(u.y);
+        if (PREV && apply) pv.u0_out[site] = u;
+      }
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const RT hl = RT(L.h * MB4_LAMBDA[i]);
       if (FIRST) {
         const double k = L.h * MB4_TC[i];
         rhs[j][i] = vec2<RT>(RT(k * f.x), RT(k * f.y));
@@ -553,7 +647,16 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
         const double2 ph = phib_in.s[i][site];
         rhs[j][i] = vec2<RT>(RT(-ph.x), RT(-ph.y));
       }
-      inv[j][i] = block_inv(blk[j], hl);
+    }
+  }
+  if (FIRST) __syncthreads();  // every read of the u_0 staging is done
+  // First sweep (from r = 0): the local 2x2 solves.
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kSolveThreads;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const RT hl = RT(L.h * MB4_LAMBDA[i]);
       sr[i][idx] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
     }
   }
@@ -606,7 +709,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
   __syncthreads();
   // Interior (valid after all sweeps) back to HBM; positions of the tile that
   // overhang the lattice are not written.
-  unsigned long long rm = 0ull;
+  NormAcc rm;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kSolveThreads;
@@ -626,13 +729,14 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const double2 d = t_apply(m, r);
-          rm = umax(rm, umax(abs_bits(d.x), abs_bits(d.y)));
+          rm.add(d.x);
+          rm.add(d.y);
         }
       }
     }
   }
-  if (rslot != nullptr) block_max_to<kSolveThreads>(rm, rslot);
-  if (FIRST) block_max_to<kSolveThreads>(um, fa.u0max_slot);
+  if (rslot != nullptr) block_max_to<kSolveThreads>(rm.bits(), rslot);
+  if (FIRST && fa.u0max_slot != nullptr) block_max_to<kSolveThreads>(um.bits(), fa.u0max_slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -652,7 +756,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
 // k_stage_solve, each region position computes the values of its (wrapped)
 // lattice site from region neighbours only.
 template <int RX, int RY, bool FROM_U0, int H, class RT>
-__global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate(Lattice L, CPlanes3 Uin, Planes3 Uout,
+__global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 Uin, Planes3 Uout,
                                                           CPlanesOf<vec2_t<RT>> rb,
                                                           PlanesOf<vec2_t<RT>> rout,
                                                           unsigned long long* rnext,
@@ -680,6 +784,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate
   tx0 *= TSX;
   ty0 *= TSY;
   const int ox = tx0 - H - 1, oy = ty0 - H - 1;  // region origin
+  const bool fast = nx >= RX + 2 && ny >= RY + 2;
 
   if (converged_at(fin)) {
     // Final update on this block's tile only.
@@ -717,7 +822,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
-    const int site = wrap(oy + ly, ny) * nx + wrap(ox + lx, nx);
+    const int site = wrap_in(oy + ly, ny, fast) * nx + wrap_in(ox + lx, nx, fast);
     gsite[j] = site;
     u0v[j] = L.u0[site];
     vv[j] = L.V[site];
@@ -765,6 +870,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate
     const int lx = idx % RX, ly = idx / RX;
     blk[j] = block_in<RT>(site_block(L, u0v[j], vv[j]));
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
+      block_invs(blk[j], L.h, inv[j]);
       const double t = L.t, g = L.g, h = L.h;
       const double vs = vv[j] + L.shift;
       double2 phi[3];
@@ -804,7 +910,6 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate
                           MB4_TINV[i][2] * phi[2].y;
         const RT hl = RT(L.h * MB4_LAMBDA[i]);
         rhs[j][i] = vec2<RT>(RT(-bp), RT(-bq));
-        inv[j][i] = block_inv(blk[j], hl);
         r1[j][i] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
       }
     }
@@ -864,7 +969,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate
   }
   __syncthreads();
   // The tile: rbar^{iter+1} back to HBM, and the update norm.
-  unsigned long long rm = 0ull;
+  NormAcc rm;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
@@ -882,11 +987,12 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_iterate
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const double2 d = t_apply(m, r);
-        rm = umax(rm, umax(abs_bits(d.x), abs_bits(d.y)));
+        rm.add(d.x);
+        rm.add(d.y);
       }
     }
   }
-  block_max_to<kIterThreads>(rm, rnext);
+  block_max_to<kIterThreads>(rm.bits(), rnext);
 }
 
 // Update pass of the last Newton iteration `fin.prev` of a batch: the final
@@ -1156,11 +1262,11 @@ CPlanesOf<vec2_t<RT>> as_r(CPlanes3 p) {
                                 reinterpret_cast<const vec2_t<RT>*>(p.s[2])}};
 }
 
-template <int RX, int RY, bool FIRST, class RT>
+template <int RX, int RY, bool FIRST, class RT, bool PREV = false>
 hipError_t launch_solve_region(const Lattice& lat, CPlanes3 phib_in, Planes3 phib_out,
                                Planes3 rout_d, unsigned long long* rslot, ConvCheck check,
                                FirstArgs fa, int sweeps, const Multi& mu, hipStream_t stream,
-                               LaunchEvents ev) {
+                               LaunchEvents ev, PrevStep pv = PrevStep{}) {
   const PlanesOf<vec2_t<RT>> rout = as_r<RT>(rout_d);
   const int h = sweeps - 1, tx = RX - 2 * h, ty = RY - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
@@ -1168,17 +1274,17 @@ hipError_t launch_solve_region(const Lattice& lat, CPlanes3 phib_in, Planes3 phi
       block(RX * RY / 2);
   switch (sweeps) {
     case 1:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 0, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
-                 rslot, check, fa, mu);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 0, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
+                 phib_out, rout, rslot, check, fa, mu, pv);
     case 2:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 1, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
-                 rslot, check, fa, mu);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 1, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
+                 phib_out, rout, rslot, check, fa, mu, pv);
     case 3:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 2, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
-                 rslot, check, fa, mu);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 2, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
+                 phib_out, rout, rslot, check, fa, mu, pv);
     case 4:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 3, FIRST, RT>), grid, block, ev, lat, phib_in, phib_out, rout,
-                 rslot, check, fa, mu);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 3, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
+                 phib_out, rout, rslot, check, fa, mu, pv);
     default:
       return hipErrorInvalidValue;
   }
@@ -1228,14 +1334,37 @@ hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, i
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
                               Planes3 phib_out, hipStream_t stream, LaunchEvents ev,
-                              const Multi& mu, int region, bool fp32) {
+                              const Multi& mu, int region, bool fp32, const PrevStep* prev) {
   const CPlanes3 none{{nullptr, nullptr, nullptr}};
   const FirstArgs fa{u0max_slot, phib_out.s[0] != nullptr};
   const ConvCheck nochk{nullptr, 0, 0.0, false};
+  if (prev != nullptr && fa.store_rhs) return hipErrorInvalidValue;
   if (fp32) {
     if (region != kRegion32x32 || fa.store_rhs) return hipErrorInvalidValue;
+    if (prev != nullptr)
+      return launch_solve_region<32, 32, true, float, true>(lat, none, phib_out, rout, rslot,
+                                                            nochk, fa, sweeps, mu, stream, ev,
+                                                            *prev);
     return launch_solve_region<32, 32, true, float>(lat, none, phib_out, rout, rslot, nochk, fa,
                                                     sweeps, mu, stream, ev);
+  }
+  if (prev != nullptr) {
+    switch (region) {
+      case kRegion32x32:
+        return launch_solve_region<32, 32, true, double, true>(lat, none, phib_out, rout, rslot,
+                                                               nochk, fa, sweeps, mu, stream, ev,
+                                                               *prev);
+      case kRegion64x16:
+        return launch_solve_region<64, 16, true, double, true>(lat, none, phib_out, rout, rslot,
+                                                               nochk, fa, sweeps, mu, stream, ev,
+                                                               *prev);
+      case kRegion32x16:
+        return launch_solve_region<32, 16, true, double, true>(lat, none, phib_out, rout, rslot,
+                                                               nochk, fa, sweeps, mu, stream, ev,
+                                                               *prev);
+      default:
+        return hipErrorInvalidValue;
+    }
   }
   switch (region) {
     case kRegion32x32:

@@ -231,12 +231,14 @@ enum KernelClass {
   kFinalUpdate = 5,
   kIterateFirst = 6,
   kIterate = 7,
-  kFinalEnd = 8,  // recorded as such, counted as kFinalUpdate
+  kFinalFirst = 8,  // final update of a step fused with the next first solve
+  kFinalEnd = 9,    // recorded as such, counted as kFinalUpdate
 };
-constexpr int kKernelClasses = 8;
+constexpr int kKernelClasses = 9;
 const char* const kKernelNames[kKernelClasses] = {
     "stage_solve_first", "stage_solve", "stage_sweep", "update_residual_first",
-    "update_residual",   "final_update", "iterate_first", "iterate"};
+    "update_residual",   "final_update", "iterate_first", "iterate",
+    "final_first"};
 
 int prof_event(mb4_state* s, hipEvent_t* ev) {
   if (s->ev_used == s->ev_pool.size()) {
@@ -335,22 +337,45 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
 // Newton iterate U^j lives in Ua (j odd) or Ub (j even); the stage solution
 // rbar^l of iteration l in ra (l odd) or rb (l even) on the fused path.
 double2* const* u_planes(mb4_state* s, int j) { return (j % 2 == 1) ? s->Ua : s->Ub; }
-double2* const* r_planes(mb4_state* s, int l) { return (l % 2 == 1) ? s->ra : s->rb; }
+double2* const* r_planes(mb4_state* s, int l) { return (l & 1) ? s->ra : s->rb; }
 CPlanes3 cp(double2* const* a) { return CPlanes3{{a[0], a[1], a[2]}}; }
 Planes3 pp(double2* const* a) { return Planes3{{a[0], a[1], a[2]}}; }
 
 // Fused path (at most four sweeps): iteration l's stage solve is enqueued as
 // part of the pass that updates iteration l - 1 (k_iterate), iteration 1's by
 // the first-solve kernel; after iteration `last` a final-update pass writes
-// u_1 over u_0 if `last` is where the step converged.
+// u_1 over u_0 if `last` is where the step converged.  Within a batch, the
+// final update of step k - 1 is fused into the first solve of step k
+// (prev_rec: step k - 1's record; emit_final = false for a step whose
+// successor takes its final update), and the stage-correction buffers
+// alternate with sigma = k * iters so that the first solve of step k does
+// not write the buffer step k - 1's final update reads.
 int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
-                             int first, int last) {
+                             int first, int last, int sigma = 0,
+                             const unsigned long long* prev_rec = nullptr,
+                             bool emit_final = true) {
+  auto rp = [&](int l) { return r_planes(s, l + sigma); };
   for (int l = first; l <= last; ++l) {
     if (l == 1) {
-      LAUNCH(s, kFirstSolve, step, 1,
-             mb4::launch_first_solve(L, pp(r_planes(s, 1)), s->sweeps, rec + 1, rec,
-                                     Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_,
-                                     mb4::Multi{}, mb4::kRegion32x32, s->fp32));
+      if (prev_rec != nullptr) {
+        // Step k - 1 ran `last` iterations too, with sigma_{k-1} = sigma - last
+        // (mod 2), so its rbar^last sits in r_planes(last + sigma_{k-1}).
+        const int sigma_prev = (sigma + last) & 1;
+        const mb4::PrevStep pv{cp(u_planes(s, last - 1)), cp(r_planes(s, last + sigma_prev)),
+                               conv_check(s, prev_rec, last - 1), conv_check(s, prev_rec, last),
+                               s->u0};
+        LAUNCH(s, kFinalFirst, step, 1,
+               mb4::launch_first_solve(L, pp(rp(1)), s->sweeps, rec + 1,
+                                       s->relative_eps ? rec : nullptr,
+                                       Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_,
+                                       mb4::Multi{}, mb4::kRegion32x32, s->fp32, &pv));
+      } else {
+        LAUNCH(s, kFirstSolve, step, 1,
+               mb4::launch_first_solve(L, pp(rp(1)), s->sweeps, rec + 1,
+                                       s->relative_eps ? rec : nullptr,
+                                       Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_,
+                                       mb4::Multi{}, mb4::kRegion32x32, s->fp32));
+      }
       continue;
     }
     const int j = l - 1;  // the iteration this pass updates
@@ -358,23 +383,21 @@ int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned 
     const ConvCheck fin = conv_check(s, rec, j);
     const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
     LAUNCH(s, kIterate, step, j,
-           mb4::launch_iterate(L, uin, pp(u_planes(s, j)), cp(r_planes(s, j)),
-                               pp(r_planes(s, l)), j == 1, s->sweeps, rec + l, chk, fin, s->u0,
-                               s->q, ev_, mb4::Multi{}, mb4::kRegion32x32, s->fp32));
+           mb4::launch_iterate(L, uin, pp(u_planes(s, j)), cp(rp(j)), pp(rp(l)), j == 1,
+                               s->sweeps, rec + l, chk, fin, s->u0, s->q, ev_, mb4::Multi{},
+                               mb4::kRegion32x32, s->fp32));
   }
+  if (!emit_final) return MB4_OK;
   const int j = last;
   const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
   const ConvCheck fin = conv_check(s, rec, j);
   const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
   LAUNCH(s, kFinalEnd, step, j,
-         mb4::launch_final_update(L, uin, cp(r_planes(s, j)), j == 1, chk, fin, s->u0, s->q,
-                                  ev_, mb4::Multi{}, s->fp32));
+         mb4::launch_final_update(L, uin, cp(rp(j)), j == 1, chk, fin, s->u0, s->q, ev_,
+                                  mb4::Multi{}, s->fp32));
   return MB4_OK;
 }
 
-// Enqueues Newton iterations first .. last of step `step` (record `rec`).
-// The update pass of the iteration whose norm meets the tolerance writes
-// u_1 = U_{c_3} over u_0; kernels of later iterations return at once.
 int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
                        int first, int last) {
   if (s->sweeps <= mb4::kMaxFusedSweeps)
@@ -450,8 +473,15 @@ void update_prediction(mb4_state* s, int batch_max) {
 int enqueue_batch(mb4_state* s, int count, int iters) {
   const Lattice L = lattice_of(s);
   HIP_TRY(mb4::launch_clear(s->ring, count * s->rec_len, s->q));
+  // A step of one iteration has u_0 as the base of its final update, which
+  // the fused kernel overwrites block by block, so only iters >= 2 fuses.
+  const bool fuse = s->sweeps <= mb4::kMaxFusedSweeps && iters >= 2;
   for (int k = 0; k < count; ++k) {
-    const int rc = enqueue_iterations(s, L, k, s->ring + size_t(k) * s->rec_len, 1, iters);
+    unsigned long long* rec = s->ring + size_t(k) * s->rec_len;
+    const int rc =
+        fuse ? enqueue_iterations_fused(s, L, k, rec, 1, iters, (k * iters) % 2,
+                                        k > 0 ? rec - s->rec_len : nullptr, k == count - 1)
+             : enqueue_iterations(s, L, k, rec, 1, iters);
     if (rc != MB4_OK) return rc;
   }
   return MB4_OK;

@@ -137,6 +137,25 @@ def test_newton_failure_keeps_the_last_accepted_step():
         assert st.steps_done() == 0
 
 
+@pytest.mark.parametrize("fp32_solve", [False, True])
+def test_non_finite_update_is_reported(fp32_solve):
+    # |psi|^2 psi overflows at one site: the Newton updates are inf/NaN, the
+    # norm reductions must keep them (a NaN is skipped by a plain max), and
+    # the step fails with the state unchanged.
+    torch_cuda()
+    cfg = L.CONFIGS["lattice32"]
+    v, p, q = L.make_inputs(cfg)
+    p = p.copy()
+    p[37] = 1e160
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, fp32_solve=fp32_solve) as st:
+        st.set_state(p, q)
+        assert st.step(2) == M.MB4_ENOCONV
+        assert "non-finite" in M.error_detail()
+        assert st.steps_done() == 0
+        pp, qq = st.get_state()
+        assert np.array_equal(pp, p) and np.array_equal(qq, q)
+
+
 def test_zero_state_stays_zero():
     torch_cuda()
     cfg = L.CONFIGS["lattice32"]
