@@ -36,43 +36,33 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per lattice site of one launch of each kernel class:
 # what the kernel must read and write once, FP64, (p, q) = 16 B per field.
-#   stage_solve_first:     u0 16 + V 8 -> rbar 48 (the residual at U = u0 is
+# The fused path (up to four sweeps) holds the Newton iterate as its
+# increment X^l = U^l - u0 (three stages, 48 B):
+#   stage_solve_first:     u0 16 + V 8 -> X^1 48 (the residual at U = u0 is
 #                          built in place from u0 and its neighbours)
+#   iterate_first, iterate: u0 16 + V 8 + X^l 48 -> X^{l+1} 48 (residual of
+#                          iteration l, the next stage solve and the update,
+#                          Phibar and rbar kept on chip)
+#   final_update:          u0 16 + X_3 16 -> u1 16
+#   final_first:           u0 16 + X_3 16 + V 8 -> u1 16 + X^1 48 (the final
+#                          update of a step fused with the next step's first
+#                          stage solve, which builds u1 on its region itself)
+# The plain path (more sweeps than the fused kernels take) keeps U and rbar:
 #   stage_solve:           u0 16 + V 8 + Phibar 48 -> rbar 48 (all fused sweeps)
 #   stage_sweep:           u0 16 + V 8 + Phibar 48 + rbar 48 -> rbar 48
 #   update_residual_first: u0 16 + V 8 + rbar 48 -> U 48 + Phibar 48
 #   update_residual:       u0 16 + V 8 + U 48 + rbar 48 -> U 48 + Phibar 48
-#   final_update:          U_3 16 + rbar 48 -> u0 16
-#   iterate_first:         u0 16 + V 8 + rbar 48 -> U 48 + rbar 48 (update of
-#                          iteration 1 from U = u0, residual and the next
-#                          stage solve, Phibar kept on chip)
-#   iterate:               u0 16 + V 8 + U 48 + rbar 48 -> U 48 + rbar 48
-#   final_first:           U_3 16 + rbar 48 + V 8 -> u0 16 + rbar 48 (the final
-#                          update of a step fused with the next step's first
-#                          stage solve, which builds u_0 on its region itself)
+# FP32 inner solves change no HBM traffic: rbar and the sweeps stay on chip.
 BYTES_PER_SITE = {
     "stage_solve_first": 72,
     "stage_solve": 120,
     "stage_sweep": 168,
     "update_residual_first": 168,
     "update_residual": 216,
-    "final_update": 80,
-    "iterate_first": 168,
-    "iterate": 216,
-    "final_first": 136,
-}
-# With FP32 inner solves the stage corrections rbar are 24 B/site instead of 48:
-#   stage_solve_first: u0 16 + V 8 -> rbar 24
-#   iterate_first:     u0 16 + V 8 + rbar 24 -> U 48 + rbar 24
-#   iterate:           u0 16 + V 8 + U 48 + rbar 24 -> U 48 + rbar 24
-#   final_update:      U_3 16 + rbar 24 -> u0 16
-#   final_first:       U_3 16 + rbar 24 + V 8 -> u0 16 + rbar 24
-BYTES_PER_SITE_FP32 = {
-    "stage_solve_first": 48,
+    "final_update": 48,
     "iterate_first": 120,
-    "iterate": 168,
-    "final_update": 56,
-    "final_first": 88,
+    "iterate": 120,
+    "final_first": 104,
 }
 
 
@@ -134,17 +124,13 @@ def cpu_baseline(sample_side: int, sample_steps: int, workload: str) -> dict:
                        f"{dt:.1f} s")}
 
 
-def step_bytes_per_site(iters: int, fp32_solve: bool = False) -> int:
+def step_bytes_per_site(iters: int) -> int:
     """Algorithmic HBM bytes per site of one whole step with `iters` Newton
     iterations inside a batch: final update fused with the first solve, then
-    the fused iterations."""
-    b = BYTES_PER_SITE_FP32 if fp32_solve else BYTES_PER_SITE
-    if iters < 2:
-        return b["stage_solve_first"] + b["final_update"]
-    # In a batch the final update of each step is fused into the next first
-    # solve (the first step's plain first solve and the last step's final
-    # update are not counted).
-    return b["final_first"] + b["iterate_first"] + b["iterate"] * (iters - 2)
+    the fused iterations (the first step's plain first solve and the last
+    step's final update are not counted)."""
+    b = BYTES_PER_SITE
+    return b["final_first"] + b["iterate"] * (iters - 1)
 
 
 def run_ensemble(args, torch, M) -> int:
@@ -189,7 +175,7 @@ def run_ensemble(args, torch, M) -> int:
     ens.close()
     sites = sum(m.nx * m.ny for m in members)
     it = max(iters)
-    step_bytes = step_bytes_per_site(it, args.fp32_solve) * sites
+    step_bytes = step_bytes_per_site(it) * sites
     result = {
         "metric": METRIC, "value": sites * steps / elapsed, "unit": UNIT, "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / steps,
@@ -206,7 +192,7 @@ def run_ensemble(args, torch, M) -> int:
         "energy_drift": drift, "energy_drift_ok": drift <= 1e-14,
         "newton_iters_last": {"min": min(iters), "max": it},
         "tuning": tuning,
-        "step_bandwidth": {"bytes_per_site_step": step_bytes_per_site(it, args.fp32_solve),
+        "step_bandwidth": {"bytes_per_site_step": step_bytes_per_site(it),
                            "achieved_GBs": step_bytes / (elapsed / steps) / 1e9,
                            "peak_GBs": HBM_PEAK_GBS},
     }
@@ -480,8 +466,7 @@ def main(argv=None) -> int:
         dominant = max(prof, key=lambda k: prof[k][1])
         n_launch, total_ms = prof[dominant]
         per_launch_s = total_ms / 1e3 / max(n_launch, 1)
-        table = BYTES_PER_SITE_FP32 if args.fp32_solve else BYTES_PER_SITE
-        bytes_launch = table[dominant] * sites
+        bytes_launch = BYTES_PER_SITE[dominant] * sites
         achieved = bytes_launch / per_launch_s / 1e9
         traffic = None if args.fp32_solve else measured_traffic(dominant, sites)
         result["roofline"] = {

@@ -95,7 +95,7 @@ typedef struct {
 #define MB4_FLAG_RELATIVE_EPS 2u
 /* mb4_options.flags: FP32 inner stage solves.  The block-Jacobi sweeps of
  * the stage systems (Eq. MB4_5), their 2x2 block inverses and right-hand
- * sides run in FP32 and the stage corrections rbar are stored in FP32; the
+ * sides run in FP32 (the stage corrections rbar never leave the chip); the
  * residual Phi, the stage quadrature, the Newton update U + (T (x) I) rbar,
  * its norm and the energy stay FP64, so the step converges to the same FP64
  * root.  At most 4 inner sweeps; mb4_newton_update and mb4_stage_solve stay
@@ -218,9 +218,9 @@ MB4_API int mb4_stage_solve(mb4_state* state, const double* d_phibar, double* d_
  * members that need more Newton iterations do not hold the others back
  * beyond the batch in which it happens.
  *
- * Member fields are stored one after the other: 216 bytes per site
- * (potential, u_0, two stage-value fields, two stage-correction fields) plus
- * the step records (8 * 32 * (max_newton + 1) bytes per member). */
+ * Member fields are stored one after the other: 136 bytes per site
+ * (potential, two u_0 buffers, two Newton-iterate fields of three stages)
+ * plus the step records (8 * 32 * (max_newton + 1) bytes per member). */
 typedef struct mb4_ensemble mb4_ensemble;
 
 /* Shapes of the solve regions (positions per block; the output tile is the
@@ -324,8 +324,7 @@ typedef struct {
 } mb4_server_info;
 
 /* Creates a server on the current device whose device memory stays within
- * arena_bytes (member fields: 216 bytes per site, 168 with
- * MB4_FLAG_FP32_SOLVE, plus step records).  max_active (1 .. 65536) bounds
+ * arena_bytes (member fields: 136 bytes per site, plus step records).  max_active (1 .. 65536) bounds
  * the requests on the GPU at once, batch_steps (1 .. 32) the steps per poll.
  * opt as for mb4_ensemble_create (inner_sweeps <= 4; mem_budget ignored).
  * Errors: MB4_EINVAL, MB4_ENOMEM, MB4_EDEVICE. */

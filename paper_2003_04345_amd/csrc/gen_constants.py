@@ -19,6 +19,9 @@ double:
   (Eq. fIu2) by a quadrature with the same value.
 * TC_i = sum_m (T^-1)_im c_m: at U = e_3 (x) u_0 the residual of stage m is
   -h c_m f(u_0), so the transformed residual is -h TC_i f(u_0).
+* E_i0 + sum_j E_ij = int_0^1 A_{c_i,zeta} dzeta = c_i (checked here): with
+  the stage values held as U_j = u_0 + X_j, the linear part of stage i is
+  c_i u_0 + sum_j E_ij X_j.
 """
 from __future__ import annotations
 
@@ -89,6 +92,10 @@ def derive():
             s = sum(q_tab[i][q] * l_tab[q][j] for q in range(6))
             assert abs(sp.N(s - e_full[i, j], DIGITS)) < sp.Float(10) ** (-40)
     tc = [sum(tinv[i, mm] * c[mm + 1] for mm in range(3)) for i in range(3)]
+    # Row sums of the full E (j = 0..3) are int_0^1 A_{c_i,zeta} dzeta (the l_j
+    # sum to one), which equal c_i: the kernels take c_i for them.
+    for i in range(3):
+        assert sp.simplify(sum(e_full[i, j] for j in range(4)) - c[i + 1]) == 0
     return {
         "c": c[1:], "e0": [e_full[i, 0] for i in range(3)],
         "e": [[e[i, j] for j in range(3)] for i in range(3)],

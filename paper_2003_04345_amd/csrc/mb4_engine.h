@@ -28,9 +28,9 @@ struct Config {
 
 struct Engine;
 
-// Bytes of device memory per site of capacity: V, u_0, two stage-value
-// fields and two stage-correction fields (FP32 ones with cfg.fp32).
-size_t bytes_per_site(bool fp32);
+// Bytes of device memory per site of capacity: V, two u_0 buffers and two
+// Newton-iterate fields (X^l, three stages each).
+size_t bytes_per_site();
 
 int create(const Config& cfg, Engine** out);
 void destroy(Engine* e);

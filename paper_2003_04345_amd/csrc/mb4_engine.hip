@@ -62,11 +62,10 @@ struct Engine {
   std::vector<void*> host_allocs;
 
   double* V = nullptr;
-  double2* u0 = nullptr;
-  double2* Ua[3] = {nullptr, nullptr, nullptr};
-  double2* Ub[3] = {nullptr, nullptr, nullptr};
-  double2* ra[3] = {nullptr, nullptr, nullptr};  // float2 planes with cfg.fp32
-  double2* rb[3] = {nullptr, nullptr, nullptr};
+  double2* u0 = nullptr;   // every member's state between batches
+  double2* u0b = nullptr;  // the other u_0 buffer of a batch
+  double2* Xa[3] = {nullptr, nullptr, nullptr};  // Newton iterates X^l (StepOut)
+  double2* Xb[3] = {nullptr, nullptr, nullptr};
   MemberDesc* d_desc = nullptr;
   int* d_block0 = nullptr;  // 4 prefix tables of max_members + 1
   int blocks[4] = {0, 0, 0, 0};
@@ -181,59 +180,57 @@ Lattice lattice_of(const Engine* e) {
 
 Planes3 pp(double2* const* a) { return Planes3{{a[0], a[1], a[2]}}; }
 CPlanes3 cp(double2* const* a) { return CPlanes3{{a[0], a[1], a[2]}}; }
-double2* const* u_planes(const Engine* e, int j) { return (j % 2 == 1) ? e->Ua : e->Ub; }
-double2* const* r_planes(const Engine* e, int l) { return (l & 1) ? e->ra : e->rb; }
+double2* const* x_planes(const Engine* e, int l) { return (l & 1) ? e->Xa : e->Xb; }
+double2* batch_u0(const Engine* e, int k) { return (k & 1) ? e->u0b : e->u0; }
 
 ConvCheck conv_check(const Engine* e, const unsigned long long* rec, int prev) {
   return ConvCheck{rec, prev, e->cfg.eps, e->cfg.relative_eps};
 }
 
 // Step `step` of a batch of `count` steps, Newton iterations 1 .. iters, every
-// member.  With iters >= 2 the final update of step k - 1 is fused into the
-// first solve of step k, only the last step of the batch has its own final
-// update, and the stage-correction buffers alternate with sigma = k * iters
-// (so the first solve of step k does not write what that final update reads).
+// member, with the iterate held as X^l = U^l - e (x) u_0 (StepOut).  Step k
+// reads u_0 from u0 (k even) or u0b (k odd) and writes u_1 to the other
+// buffer; a member's last step of the batch writes it to u0.  The final
+// update of step k - 1 is fused into the first solve of step k, only the last
+// step of the batch has its own final update, and the X buffers alternate
+// with sigma = k * iters (so the first solve of step k does not write what
+// that final update reads).
 int enqueue_step(Engine* e, int step, int count, int iters) {
-  const Lattice L = lattice_of(e);
+  Lattice L = lattice_of(e);
+  double2* const src = batch_u0(e, step);
+  L.u0 = src;
+  const StepOut so{step == count - 1 ? e->u0 : batch_u0(e, step + 1), e->u0};
   const int members = int(e->desc.size());
   unsigned long long* rec = e->ring + size_t(step) * members * e->rec_len;
   const Multi mf = multi_of(e, kFirst, step), mi = multi_of(e, kIter, step),
               mfin = multi_of(e, kFinal, step);
   const bool f32 = e->cfg.fp32;
-  const bool fuse = iters >= 2;
-  const int sigma = fuse ? (step * iters) & 1 : 0;
-  auto rp = [&](int l) { return r_planes(e, l + sigma); };
-  if (fuse && step > 0) {
+  const ConvCheck none{nullptr, 0, 0.0, false};
+  const int sigma = (step * iters) & 1;
+  auto xp = [&](int l) { return x_planes(e, l + sigma); };
+  unsigned long long* const u0max = e->cfg.relative_eps ? rec : nullptr;
+  if (step > 0) {
     const unsigned long long* prev = rec - size_t(members) * e->rec_len;
     const int sigma_prev = (sigma + iters) & 1;
-    const PrevStep pv{cp(u_planes(e, iters - 1)), cp(r_planes(e, iters + sigma_prev)),
-                      conv_check(e, prev, iters - 1), conv_check(e, prev, iters), e->u0};
-    HIP_TRY(launch_first_solve(L, pp(rp(1)), e->cfg.sweeps, rec + 1,
-                               e->cfg.relative_eps ? rec : nullptr,
-                               Planes3{{nullptr, nullptr, nullptr}}, e->q, {}, mf, e->region,
-                               f32, &pv));
+    const PrevStep pv{batch_u0(e, step - 1), cp(x_planes(e, iters + sigma_prev)),
+                      iters >= 2 ? conv_check(e, prev, iters - 1) : none,
+                      conv_check(e, prev, iters), src, e->u0};
+    HIP_TRY(launch_first_solve_x(L, pp(xp(1)), e->cfg.sweeps, rec + 1, u0max, e->q, {}, mf,
+                                 e->region, f32, &pv));
   } else {
-    HIP_TRY(launch_first_solve(L, pp(rp(1)), e->cfg.sweeps, rec + 1,
-                               e->cfg.relative_eps ? rec : nullptr,
-                               Planes3{{nullptr, nullptr, nullptr}}, e->q, {}, mf, e->region,
-                               f32));
+    HIP_TRY(launch_first_solve_x(L, pp(xp(1)), e->cfg.sweeps, rec + 1, u0max, e->q, {}, mf,
+                                 e->region, f32, nullptr));
   }
   for (int l = 2; l <= iters; ++l) {
     const int j = l - 1;
-    const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
-    const ConvCheck fin = conv_check(e, rec, j);
-    const CPlanes3 uin = j >= 2 ? cp(u_planes(e, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
-    HIP_TRY(launch_iterate(L, uin, pp(u_planes(e, j)), cp(rp(j)), pp(rp(l)), j == 1,
-                           e->cfg.sweeps, rec + l, chk, fin, e->u0, e->q, {}, mi, e->region,
-                           f32));
+    const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : none;
+    HIP_TRY(launch_iterate(L, cp(xp(j)), pp(xp(l)), e->cfg.sweeps, rec + l, chk,
+                           conv_check(e, rec, j), so, e->q, {}, mi, e->region, f32));
   }
-  if (fuse && step + 1 < count) return MB4_OK;  // step + 1 takes the final update
-  const int j = iters;
-  const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
-  const ConvCheck fin = conv_check(e, rec, j);
-  const CPlanes3 uin = j >= 2 ? cp(u_planes(e, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
-  HIP_TRY(launch_final_update(L, uin, cp(rp(j)), j == 1, chk, fin, e->u0, e->q, {}, mfin,
-                              f32));
+  if (step + 1 < count) return MB4_OK;  // step + 1 takes the final update
+  const ConvCheck chk = iters >= 2 ? conv_check(e, rec, iters - 1) : none;
+  HIP_TRY(launch_final_update(L, cp(xp(iters)), chk, conv_check(e, rec, iters), so, e->q, {},
+                              mfin));
   return MB4_OK;
 }
 
@@ -311,7 +308,7 @@ void update_prediction(Engine* e, int batch_max) {
 
 }  // namespace
 
-size_t bytes_per_site(bool fp32) { return 8 + 16 + 2 * 48 + 2 * (fp32 ? 24 : 48); }
+size_t bytes_per_site() { return 8 + 2 * 16 + 2 * 48; }
 
 int create(const Config& cfg, Engine** out) {
   *out = nullptr;
@@ -332,14 +329,12 @@ int create(const Config& cfg, Engine** out) {
   hipError_t err = hipGetDevice(&e->device);
   if (err != hipSuccess) rc = fail(MB4_EDEVICE, "hipGetDevice: %s", hipGetErrorString(err));
   const size_t field = sizeof(double2) * cfg.capacity;
-  const size_t rfield = (cfg.fp32 ? sizeof(float2) : sizeof(double2)) * cfg.capacity;
   if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->V), sizeof(double) * cfg.capacity);
   if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->u0), field);
+  if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->u0b), field);
   for (int i = 0; i < 3 && rc == MB4_OK; ++i) {
-    rc = dalloc(e, reinterpret_cast<void**>(&e->Ua[i]), field);
-    if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->Ub[i]), field);
-    if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->ra[i]), rfield);
-    if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->rb[i]), rfield);
+    rc = dalloc(e, reinterpret_cast<void**>(&e->Xa[i]), field);
+    if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->Xb[i]), field);
   }
   const size_t mm = size_t(cfg.max_members);
   if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->d_desc), sizeof(MemberDesc) * mm);
@@ -401,7 +396,7 @@ int upload(Engine* e, long long base, size_t n, const double* V, const double* p
   hipStream_t s = e->cfg.stream;
   if (V != nullptr)
     HIP_TRY(hipMemcpyAsync(e->V + base, V, sizeof(double) * n, hipMemcpyHostToDevice, s));
-  double* stage = reinterpret_cast<double*>(e->Ua[0] + base);  // scratch between batches
+  double* stage = reinterpret_cast<double*>(e->Xa[0] + base);  // scratch between batches
   HIP_TRY(hipMemcpyAsync(stage, p, sizeof(double) * n, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(stage + n, q, sizeof(double) * n, hipMemcpyHostToDevice, s));
   HIP_TRY(launch_interleave(stage, stage + n, e->u0 + base, int(n), s));
@@ -412,7 +407,7 @@ int upload(Engine* e, long long base, size_t n, const double* V, const double* p
 int download(Engine* e, long long base, size_t n, double* p, double* q) {
   HIP_TRY(hipSetDevice(e->device));
   hipStream_t s = e->cfg.stream;
-  double* stage = reinterpret_cast<double*>(e->Ua[0] + base);
+  double* stage = reinterpret_cast<double*>(e->Xa[0] + base);
   HIP_TRY(launch_deinterleave(e->u0 + base, stage, stage + n, int(n), s));
   HIP_TRY(hipMemcpyAsync(p, stage, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(q, stage + n, sizeof(double) * n, hipMemcpyDeviceToHost, s));

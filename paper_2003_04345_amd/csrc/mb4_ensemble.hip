@@ -53,8 +53,8 @@ int check_member(const mb4_ensemble* e, int32_t m) {
 }
 
 // Device bytes of an ensemble (see mb4.h).
-size_t footprint_bytes(size_t total, int count, int max_newton, bool fp32) {
-  return total * eng::bytes_per_site(fp32) + size_t(kBatch) * count * (max_newton + 1) * 8 +
+size_t footprint_bytes(size_t total, int count, int max_newton) {
+  return total * eng::bytes_per_site() + size_t(kBatch) * count * (max_newton + 1) * 8 +
          size_t(count) * 120 + total / 256 * 12 * sizeof(double);
 }
 
@@ -113,7 +113,7 @@ int mb4_ensemble_create(int32_t count, const mb4_lattice* lattices,
   if (size_t(kBatch) * size_t(count) * size_t(o.max_newton + 1) > size_t(INT32_MAX))
     return fail(MB4_EINVAL, "count * (max_newton + 1) too large for the step records");
   const bool fp32 = (o.flags & MB4_FLAG_FP32_SOLVE) != 0;
-  const size_t need = footprint_bytes(total, count, o.max_newton, fp32);
+  const size_t need = footprint_bytes(total, count, o.max_newton);
   if (o.mem_budget != 0 && need > o.mem_budget)
     return fail(MB4_ENOMEM, "ensemble needs %zu bytes, above mem_budget %llu", need,
                 static_cast<unsigned long long>(o.mem_budget));

@@ -98,30 +98,6 @@ hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
 // not NULL: the Lattice then carries ensemble-wide V and u0, planes and
 // records are those of member 0, and `region` picks the solve-region shape.
 // Members with todo[m] <= mu.step do nothing.
-//
-// fp32: the FP32 inner stage solves.  The stage corrections rbar (rout, rbar)
-// are float2 planes (the Planes3 pointers are reinterpreted), and the
-// block-Jacobi sweeps, the 2x2 block inverses and the right-hand side -Phibar
-// are rounded to and computed in FP32.  The residual Phi, the stage
-// quadrature, the update U + (T (x) I) rbar and the norms stay FP64.  Only
-// the 32 x 32 region exists in this precision.
-
-// The final update of the previous step, fused into the first solve of the
-// next: if that step converged at its last iteration (`fin` holds, `chk`
-// does not), the region's u_0 is u_1 = U[2] + (T rbar)_3 and each block
-// writes it over u0_out for its tile; otherwise u_0 is read as it is (the
-// step converged earlier and an update pass wrote u_1, or it did not converge
-// and u_0 kept its value).  U[2] must be U_3 of an iteration >= 1 (a step of
-// one iteration has base u_0, which the blocks overwrite, so it is not
-// fused), and rbar must not be the plane set the first solve writes.  With a
-// Multi, the records are member 0's and a member whose previous step was its
-// last in the batch gets only its final update.
-struct PrevStep {
-  CPlanes3 U;
-  CPlanes3 rbar;  // float2 planes with fp32
-  ConvCheck chk, fin;
-  double2* u0_out;
-};
 
 // Newton iteration 1, stage solve: `sweeps` (1..4) block-Jacobi sweeps of
 // (I - h lambda_i J) r_i = -Phibar_i with Phibar_i = -h TC_i f(u_0) (the
@@ -130,9 +106,7 @@ struct PrevStep {
 // and writes that Phibar to phib_out when phib_out.s[0] is not NULL.
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
-                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {},
-                              const Multi& mu = {}, int region = kRegion32x32,
-                              bool fp32 = false, const PrevStep* prev = nullptr);
+                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev = {});
 
 // Newton iteration l >= 2 (or a kernel-level call), stage solve: `sweeps`
 // (1..4) block-Jacobi sweeps from r = 0 for the three stage systems
@@ -162,25 +136,73 @@ hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout
                                   unsigned long long* rslot, ConvCheck check, ConvCheck fin,
                                   double2* u0_out, hipStream_t stream, LaunchEvents ev = {});
 
-// Newton iteration `iter` fused with the stage solve of iteration iter + 1:
-// unless `check` says an earlier iteration converged (then nothing) or `fin`
-// says iteration iter converged (then the final update of u0_out, as in
-// launch_update_residual), Uout <- base + (T (x) I) rbar (base = Uin, or
-// e_3 (x) u_0 if from_u0), Phibar of Uout, then `sweeps` (1..4) block-Jacobi
-// sweeps of the stage systems into rout, and ||(T (x) I) rout||_inf into
-// *rnext.  Uin/Uout and rbar/rout must not alias.
-hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
-                          Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
-                          ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
-                          LaunchEvents ev = {}, const Multi& mu = {},
+// ---------------------------------------------------------------------------
+// The fused path (at most four sweeps per stage solve) holds the Newton
+// iterate of a step as its increment over u_0, X^l = U^l - e (x) u_0
+// (Eq. MB4_6 summed: X^l = (T (x) I)(rbar^1 + ... + rbar^l), X^0 = 0), so
+// that an iteration reads u_0, V and X^{l-1} and writes only X^l.  u_1 =
+// u_0 + X_3 (Sec. 2.2: c_3 = 1).
+//
+// Within a batch of steps u_0 alternates between two buffers: step k reads
+// Lattice::u0 and sends its u_1 to `next` (the other buffer), except that the
+// last step a member takes in the batch (k = todo[m] - 1 with a Multi; the
+// caller passes next = home on the batch's last step otherwise) sends it to
+// `home`, where the batch started.  Writes to next are never read by the same
+// launch; u_1 goes to `home` site by site only (final updates), so home may
+// be the step's own u_0.
+struct StepOut {
+  double2* next;
+  double2* home;
+};
+
+// The final update of the previous step, fused into the first solve of the
+// next.  Unless the previous step converged before its last iteration (`chk`
+// holds: an update pass already wrote its u_1, which is this step's u_0), the
+// region's u_0 is formed from the previous step's u_0 and X (u_0 + X_3 if it
+// converged at its last iteration, `fin`; u_0 itself if it did not converge,
+// so that the step repeats), and each block writes it for its tile to `next`,
+// a writable alias of this step's Lattice::u0.  With a Multi, the records are
+// member 0's, and a member whose previous step was its last in the batch gets
+// only that final update, written to `home`.
+struct PrevStep {
+  const double2* u0;  // u_0 of the previous step
+  CPlanes3 X;         // its X at the last iteration
+  ConvCheck chk, fin;
+  double2* next;
+  double2* home;
+};
+
+// Newton iteration 1 of the fused path: as launch_first_solve, the residual at
+// X^0 = 0 built in place and `sweeps` (1..4) block-Jacobi sweeps, writing
+// X^1 = (T (x) I) rbar^1 to xout (and its norm to *rslot).  prev: the fused
+// final update of the previous step (NULL: none).
+//
+// fp32: the FP32 inner stage solves.  The block-Jacobi sweeps, the 2x2 block
+// inverses and the right-hand side -Phibar are rounded to and computed in
+// FP32; the residual Phi, the stage quadrature, X, the update and the norms
+// stay FP64.  Only the 32 x 32 region exists in this precision.
+hipError_t launch_first_solve_x(const Lattice& lat, Planes3 xout, int sweeps,
+                                unsigned long long* rslot, unsigned long long* u0max_slot,
+                                hipStream_t stream, LaunchEvents ev, const Multi& mu, int region,
+                                bool fp32, const PrevStep* prev);
+
+// Newton iteration `iter` >= 1 of the fused path fused with the stage solve
+// of iteration iter + 1: unless `check` says an earlier iteration converged
+// (then nothing) or `fin` says iteration iter converged (then u_1 = u_0 +
+// X^iter_3 to so, site by site), Phibar of U^iter = u_0 + Xin, `sweeps` (1..4)
+// block-Jacobi sweeps of the stage systems, Xout <- Xin + (T (x) I) rbar^{iter+1}
+// and ||(T (x) I) rbar^{iter+1}||_inf into *rnext.  Xin and Xout must not alias.
+hipError_t launch_iterate(const Lattice& lat, CPlanes3 Xin, Planes3 Xout, int sweeps,
+                          unsigned long long* rnext, ConvCheck check, ConvCheck fin, StepOut so,
+                          hipStream_t stream, LaunchEvents ev = {}, const Multi& mu = {},
                           int region = kRegion32x32, bool fp32 = false);
 
-// Update pass of the last iteration of a batch: the final update of u0_out if
-// `fin` holds and `check` does not; nothing otherwise.
-hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
-                               ConvCheck check, ConvCheck fin, double2* u0_out,
-                               hipStream_t stream, LaunchEvents ev = {}, const Multi& mu = {},
-                               bool fp32 = false);
+// Final update of the last step of a batch, site by site: unless `check` says
+// an update pass already wrote u_1, u_1 = u_0 + X_3 if `fin` holds, u_0
+// otherwise (the step did not converge), to so.
+hipError_t launch_final_update(const Lattice& lat, CPlanes3 X, ConvCheck check, ConvCheck fin,
+                               StepOut so, hipStream_t stream, LaunchEvents ev = {},
+                               const Multi& mu = {});
 
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -502,10 +502,14 @@ __device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v,
 // by default; Region lists the shapes built), two per thread, so the tile
 // shrinks as the halo grows.
 //
-// FIRST: Newton iteration 1.  The right-hand side -Phibar_i = h TC_i f(u_0)
-// is built in place (TC = T^-1 c) from u_0 staged in LDS on the region plus
-// a one-site ring; ||u_0||_inf goes to *u0max_slot; with store_rhs the tile's
-// Phibar is also written out (for extra plain sweeps).
+// Modes: kSolvePlain takes -Phibar from phib_in and writes rbar.  The others
+// are Newton iteration 1: the right-hand side -Phibar_i = h TC_i f(u_0) is
+// built in place (TC = T^-1 c) from u_0 staged in LDS on the region plus a
+// one-site ring.  kSolveFirst writes rbar (with store_rhs the tile's Phibar
+// too, for extra plain sweeps); kSolveFirstX writes X^1 = (T (x) I) rbar
+// instead (the fused path), and kSolveFirstXPrev also applies the previous
+// step's final update (PrevStep) to the u_0 it stages.  ||u_0||_inf goes to
+// *u0max_slot if that is not NULL.
 __host__ __device__ constexpr int region_x(int region) {
   return region == kRegion64x16 ? 64 : 32;
 }
@@ -513,43 +517,49 @@ __host__ __device__ constexpr int region_y(int region) {
   return region == kRegion32x32 ? 32 : 16;
 }
 
+enum SolveMode : int { kSolvePlain = 0, kSolveFirst = 1, kSolveFirstX = 2, kSolveFirstXPrev = 3 };
+
 struct FirstArgs {
   unsigned long long* u0max_slot;  // ||u_0||_inf target
   bool store_rhs;                  // also write Phibar of the tile
 };
 
-template <int RX, int RY, int H, bool FIRST, class RT, bool PREV>
-__global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(Lattice L, CPlanes3 phib_in,
-                                                              Planes3 phib_out,
-                                                              PlanesOf<vec2_t<RT>> rout,
-                                                              unsigned long long* rslot,
-                                                              ConvCheck chk, FirstArgs fa,
-                                                              Multi mu, PrevStep pv) {
+// Where member m's u_1 of this step goes (StepOut).
+__device__ __forceinline__ double2* step_dst(const StepOut& so, const Multi& mu, int m) {
+  return (mu.todo != nullptr && mu.step == mu.todo[m] - 1) ? so.home : so.next;
+}
+
+template <int RX, int RY, int H, int MODE, class RT>
+__global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(
+    Lattice L, CPlanes3 phib_in, Planes3 phib_out, Planes3 out, unsigned long long* rslot,
+    ConvCheck chk, FirstArgs fa, Multi mu, PrevStep pv) {
+  constexpr bool FIRST = MODE != kSolvePlain;
+  constexpr bool XOUT = MODE == kSolveFirstX || MODE == kSolveFirstXPrev;
+  constexpr bool PREV = MODE == kSolveFirstXPrev;
+  static_assert(XOUT || sizeof(RT) == sizeof(double), "FP32 solves exist on the fused path only");
   using R2 = vec2_t<RT>;
   constexpr int kSolveThreads = RX * RY / 2;
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
-  // PREV: the final update of the previous step, if it converged at its last
-  // iteration (see PrevStep).
-  bool apply = false;
-  CPlanesOf<R2> prb{};
+  // PREV: how this step's u_0 is formed (PrevStep): 0 as it is, 1 the
+  // previous step's u_0 + X_3, 2 the previous step's u_0 (it did not
+  // converge).
+  int pmode = 0;
   if (PREV) {
     if (mu.todo != nullptr && mu.step - 1 >= mu.todo[w.m]) return;
     offset_check(pv.chk, w.rec);
     offset_check(pv.fin, w.rec);
-    apply = !converged_at(pv.chk) && converged_at(pv.fin);
-    offset_planes(pv.U, w.base);
-    pv.u0_out = offset_ptr(pv.u0_out, w.base);
-    // rbar has element type R2: reinterpret first, then offset by sites.
-#pragma unroll
-    for (int i = 0; i < 3; ++i) prb.s[i] = reinterpret_cast<const R2*>(pv.rbar.s[i]);
-    offset_planes(prb, w.base);
+    pmode = converged_at(pv.chk) ? 0 : (converged_at(pv.fin) ? 1 : 2);
+    pv.u0 = offset_ptr(pv.u0, w.base);
+    offset_planes(pv.X, w.base);
+    pv.next = offset_ptr(pv.next, w.base);
+    pv.home = offset_ptr(pv.home, w.base);
   }
-  if (w.skip && !(PREV && apply)) return;
+  if (w.skip && pmode == 0) return;
   offset_check(chk, w.rec);
   if (converged_at(chk)) return;
   offset_planes(phib_in, w.base);
   offset_planes(phib_out, w.base);
-  offset_planes(rout, w.base);
+  offset_planes(out, w.base);
   rslot = offset_ptr(rslot, w.rec);
   fa.u0max_slot = offset_ptr(fa.u0max_slot, w.rec);
   constexpr int RN = RX * RY;
@@ -568,17 +578,19 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
   tx0 *= TSX;
   ty0 *= TSY;
   const bool fast = nx >= RX + 2 && ny >= RY + 2;
-  // u_1 of the previous step at one site.
-  auto u_new = [&](int site) {
-    double2 r[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) r[m] = to_d2(prb.s[m][site]);
-    const double2 base = pv.U.s[2][site];
-    const double2 d = t_apply(2, r);
-    return make_double2(base.x + d.x, base.y + d.y);
+  // This step's u_0 at one site when it comes from the previous step.
+  auto u_prev = [&](int site) {
+    double2 u = pv.u0[site];
+    if (pmode == 1) {
+      const double2 x = pv.X.s[2][site];
+      u.x += x.x;
+      u.y += x.y;
+    }
+    return u;
   };
   if (PREV && w.skip) {
     // The member took its last step of the batch: only its final update.
+    if (pmode == 2 && pv.home == pv.u0) return;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int idx = threadIdx.x + j * kSolveThreads;
@@ -586,7 +598,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
       if (lx >= H && lx < H + TSX && ly >= H && ly < H + TSY && tx0 + lx - H < nx &&
           ty0 + ly - H < ny) {
         const int site = (ty0 + ly - H) * nx + (tx0 + lx - H);
-        pv.u0_out[site] = u_new(site);
+        pv.home[site] = u_prev(site);
       }
     }
     return;
@@ -608,7 +620,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
       const int ex = e % UX, ey = e / UX;
       const int site =
           wrap_in(ty0 - H - 1 + ey, ny, fast) * nx + wrap_in(tx0 - H - 1 + ex, nx, fast);
-      su[e] = (PREV && apply) ? u_new(site) : L.u0[site];
+      su[e] = (PREV && pmode != 0) ? u_prev(site) : L.u0[site];
     }
     __syncthreads();
   }
@@ -630,12 +642,12 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
     double2 f = make_double2(0.0, 0.0);
     if (FIRST) {
       f = f_from(L, u, v, su[e - 1], su[e + 1], su[e - UX], su[e + UX]);
-      const bool out = lx >= H && lx < H + TSX && ly >= H && ly < H + TSY &&
-                       tx0 + lx - H < nx && ty0 + ly - H < ny;
-      if (out) {
+      const bool tile = lx >= H && lx < H + TSX && ly >= H && ly < H + TSY &&
+                        tx0 + lx - H < nx && ty0 + ly - H < ny;
+      if (tile) {
         um.add(u.x);
         um.add(u.y);
-        if (PREV && apply) pv.u0_out[site] = u;
+        if (PREV && pmode != 0) pv.next[site] = u;
       }
     }
 #pragma unroll
@@ -719,16 +731,16 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
       double2 r[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const R2 ri = sr[i][idx];
-        rout.s[i][gsite[j]] = ri;
-        r[i] = to_d2(ri);
+        r[i] = to_d2(sr[i][idx]);
+        if (!XOUT) out.s[i][gsite[j]] = r[i];
         if (FIRST && fa.store_rhs)
           phib_out.s[i][gsite[j]] = make_double2(-double(rhs[j][i].x), -double(rhs[j][i].y));
       }
-      if (rslot != nullptr) {
+      if (XOUT || rslot != nullptr) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const double2 d = t_apply(m, r);
+          if (XOUT) out.s[m][gsite[j]] = d;
           rm.add(d.x);
           rm.add(d.y);
         }
@@ -740,28 +752,29 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
 }
 
 // ---------------------------------------------------------------------------
-// One Newton iteration's update and residual fused with the next iteration's
-// stage solve, so that Phibar never goes through HBM.  For iteration `iter`:
-//   U^iter = U^{iter-1} + (T (x) I) rbar^iter        (Eq. MB4_6; U^0 = e_3 (x) u_0)
-//   Phibar^iter = (T^-1 (x) I) Phi(U^iter)           (Eqs. Phidefinition, MB4_4)
+// One Newton iteration's residual fused with the next iteration's stage solve,
+// so that Phibar never goes through HBM.  The iterate is held as X^iter =
+// U^iter - e (x) u_0 (StepOut).  For iteration `iter`:
+//   Phibar^iter = (T^-1 (x) I) Phi(u_0 + X^iter)          (Eqs. Phidefinition, MB4_4)
 //   rbar^{iter+1} = H + 1 block-Jacobi sweeps on (I - h lambda_i J) r = -Phibar^iter
+//   X^{iter+1} = X^iter + (T (x) I) rbar^{iter+1}           (Eq. MB4_6)
 //   rec[iter + 1] = ||(T (x) I) rbar^{iter+1}||_inf
 // unless iteration iter already met the tolerance, in which case the block
-// writes u_1 = U_3^{iter-1} + (T rbar^iter)_3 over u_0 for its tile (Sec. 2.2:
-// c_3 = 1) and stops.  A block works on an RX x RY region (32 x 32 with 512
-// threads by default), two positions per thread: W_i (Eq. fKu2) on the whole
-// region in LDS, the residual on the region less one ring, the sweeps on
-// shrinking rings, and the (RX - 2 - 2H) x (RY - 2 - 2H) tile in the middle
-// is written back.  As in
-// k_stage_solve, each region position computes the values of its (wrapped)
+// writes u_1 = u_0 + X^iter_3 for its tile (Sec. 2.2: c_3 = 1) and stops.
+// With U_i = u_0 + X_i, the stage-i linear term is c_i u_0 + sum_j E_ij X_j
+// (the E_ij with j = 0..3 sum to c_i), the quadrature nodes are z_q = u_0 +
+// sum_j L_qj X_j (the l_j sum to one) and the residual is X_i - h (...).
+// A block works on an RX x RY region (32 x 32 with 512 threads by default),
+// two positions per thread: W_i (Eq. fKu2) on the whole region in LDS, the
+// residual on the region less one ring, the sweeps on shrinking rings, and
+// the (RX - 2 - 2H) x (RY - 2 - 2H) tile in the middle is written back.  As
+// in k_stage_solve, each region position computes the values of its (wrapped)
 // lattice site from region neighbours only.
-template <int RX, int RY, bool FROM_U0, int H, class RT>
-__global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 Uin, Planes3 Uout,
-                                                          CPlanesOf<vec2_t<RT>> rb,
-                                                          PlanesOf<vec2_t<RT>> rout,
+template <int RX, int RY, int H, class RT>
+__global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 Xin, Planes3 Xout,
                                                           unsigned long long* rnext,
                                                           ConvCheck chk, ConvCheck fin,
-                                                          double2* u0_out, Multi mu) {
+                                                          StepOut so, Multi mu) {
   using R2 = vec2_t<RT>;
   constexpr int kIterThreads = RX * RY / 2;
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
@@ -769,12 +782,9 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
   offset_check(chk, w.rec);
   if (converged_at(chk)) return;
   offset_check(fin, w.rec);
-  offset_planes(Uin, w.base);
-  offset_planes(Uout, w.base);
-  offset_planes(rb, w.base);
-  offset_planes(rout, w.base);
+  offset_planes(Xin, w.base);
+  offset_planes(Xout, w.base);
   rnext = offset_ptr(rnext, w.rec);
-  u0_out = offset_ptr(u0_out, w.base);
   constexpr int RN = RX * RY;
   constexpr int TSX = RX - 2 - 2 * H, TSY = RY - 2 - 2 * H;
   constexpr int PER = RN / kIterThreads;
@@ -788,6 +798,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
 
   if (converged_at(fin)) {
     // Final update on this block's tile only.
+    double2* const dst = offset_ptr(step_dst(so, mu, w.m), w.base);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int idx = threadIdx.x + j * kIterThreads;
@@ -795,12 +806,8 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
       if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY &&
           ox + lx < nx && oy + ly < ny) {
         const int site = (oy + ly) * nx + (ox + lx);
-        double2 r[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) r[m] = to_d2(rb.s[m][site]);
-        const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
-        const double2 d = t_apply(2, r);
-        u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
+        const double2 u = L.u0[site], x = Xin.s[2][site];
+        dst[site] = make_double2(u.x + x.x, u.y + x.y);
       }
     }
     return;
@@ -811,13 +818,10 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
   R2(*const si)[RN] = reinterpret_cast<R2(*)[RN]>(&sb[0][0]);
   int gsite[PER];
   double2 u0v[PER];
-  double2 Un[PER][3];
+  double2 xv[PER][3];
   double vv[PER];
-  // Phase 1: U^iter and W_i on the whole region.  Every load of both
-  // positions is issued before the first store, so that their latencies
-  // overlap (the compiler cannot move loads across the stores of U^iter).
-  double2 ldu[PER][3];
-  R2 ldr[PER][3];
+  // Phase 1: W_i on the whole region.  Every load of both positions is
+  // issued before the first LDS store, so that their latencies overlap.
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
@@ -827,43 +831,25 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
     u0v[j] = L.u0[site];
     vv[j] = L.V[site];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      ldr[j][i] = rb.s[i][site];
-      if (!FROM_U0) ldu[j][i] = Uin.s[i][site];
-    }
+    for (int i = 0; i < 3; ++i) xv[j][i] = Xin.s[i][site];
   }
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
-    const int lx = idx % RX, ly = idx / RX;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double2 base = FROM_U0 ? u0v[j] : ldu[j][i];
-      const double2 rj[3] = {to_d2(ldr[j][0]), to_d2(ldr[j][1]), to_d2(ldr[j][2])};
-      const double2 d = t_apply(i, rj);
-      Un[j][i] = make_double2(base.x + d.x, base.y + d.y);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      sb[i][idx] = make_double2(MB4_E0[i] * u0v[j].x + MB4_E[i][0] * Un[j][0].x +
-                                    MB4_E[i][1] * Un[j][1].x + MB4_E[i][2] * Un[j][2].x,
-                                MB4_E0[i] * u0v[j].y + MB4_E[i][0] * Un[j][0].y +
-                                    MB4_E[i][1] * Un[j][1].y + MB4_E[i][2] * Un[j][2].y);
-    }
-    // U^iter of the tile goes out now, while it is in registers.
-    if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY && ox + lx < nx &&
-        oy + ly < ny) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) Uout.s[i][gsite[j]] = Un[j][i];
+      sb[i][idx] = make_double2(MB4_C[i] * u0v[j].x + MB4_E[i][0] * xv[j][0].x +
+                                    MB4_E[i][1] * xv[j][1].x + MB4_E[i][2] * xv[j][2].x,
+                                MB4_C[i] * u0v[j].y + MB4_E[i][0] * xv[j][0].y +
+                                    MB4_E[i][1] * xv[j][1].y + MB4_E[i][2] * xv[j][2].y);
     }
   }
   __syncthreads();
 
-  // Phase 2: residual, transform and first (local) sweep on ring >= 1.
+  // Phase 2: residual and transform on ring >= 1.
   R2 rhs[PER][3];
   SiteBlockT<RT> blk[PER];
   RT inv[PER][3];
-  R2 r1[PER][3];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
@@ -885,10 +871,10 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        const double zp = MB4_GL_L[q][0] * u0v[j].x + MB4_GL_L[q][1] * Un[j][0].x +
-                          MB4_GL_L[q][2] * Un[j][1].x + MB4_GL_L[q][3] * Un[j][2].x;
-        const double zq = MB4_GL_L[q][0] * u0v[j].y + MB4_GL_L[q][1] * Un[j][0].y +
-                          MB4_GL_L[q][2] * Un[j][1].y + MB4_GL_L[q][3] * Un[j][2].y;
+        const double zp = u0v[j].x + MB4_GL_L[q][1] * xv[j][0].x +
+                          MB4_GL_L[q][2] * xv[j][1].x + MB4_GL_L[q][3] * xv[j][2].x;
+        const double zq = u0v[j].y + MB4_GL_L[q][1] * xv[j][0].y +
+                          MB4_GL_L[q][2] * xv[j][1].y + MB4_GL_L[q][3] * xv[j][2].y;
         const double gn = g * (zp * zp + zq * zq);
         const double fp = gn * zq, fq = -gn * zp;
 #pragma unroll
@@ -899,8 +885,8 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        phi[i].x = (Un[j][i].x - u0v[j].x) - h * phi[i].x;
-        phi[i].y = (Un[j][i].y - u0v[j].y) - h * phi[i].y;
+        phi[i].x = xv[j][i].x - h * phi[i].x;
+        phi[i].y = xv[j][i].y - h * phi[i].y;
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -908,20 +894,23 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
                           MB4_TINV[i][2] * phi[2].x;
         const double bq = MB4_TINV[i][0] * phi[0].y + MB4_TINV[i][1] * phi[1].y +
                           MB4_TINV[i][2] * phi[2].y;
-        const RT hl = RT(L.h * MB4_LAMBDA[i]);
         rhs[j][i] = vec2<RT>(RT(-bp), RT(-bq));
-        r1[j][i] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
       }
     }
   }
   __syncthreads();  // every stencil read of W is done
+  // First sweep (from r = 0, local) on ring >= 1, formed only now so that
+  // its values need no registers across the barrier.
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) si[i][idx] = r1[j][i];
+      for (int i = 0; i < 3; ++i) {
+        const RT hl = RT(L.h * MB4_LAMBDA[i]);
+        si[i][idx] = block_solve_t(blk[j], hl, inv[j][i], rhs[j][i].x, rhs[j][i].y);
+      }
     }
   }
   // Sweeps 2 .. H+1 on ring >= 2, one stage at a time with one barrier per
@@ -958,6 +947,24 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
       }
     }
   }
+  // X^iter of the tile again (its first read is likely still in L2): holding
+  // it in registers through the sweeps would spill.
+  // Tile positions never wrap, so their site is formed afresh here (reusing
+  // the phase-1 addresses would keep them live, and spilled, all along).
+  int tsite[PER];
+  double2 xt[PER][3];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = threadIdx.x + j * kIterThreads;
+    const int lx = idx % RX, ly = idx / RX;
+    const bool tile = lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY &&
+                      ox + lx < nx && oy + ly < ny;
+    tsite[j] = tile ? (oy + ly) * nx + (ox + lx) : -1;
+    if (tile) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) xt[j][m] = Xin.s[m][tsite[j]];
+    }
+  }
   if (H > 0) {
     __syncthreads();
 #pragma unroll
@@ -968,25 +975,19 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
     }
   }
   __syncthreads();
-  // The tile: rbar^{iter+1} back to HBM, and the update norm.
+  // The tile: X^{iter+1} back to HBM, and the update norm.
   NormAcc rm;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
-    const int lx = idx % RX, ly = idx / RX;
-    if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY && ox + lx < nx &&
-        oy + ly < ny) {
-      const int site = gsite[j];
+    if (tsite[j] >= 0) {
       double2 r[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const R2 ri = si[i][idx];
-        rout.s[i][site] = ri;
-        r[i] = to_d2(ri);
-      }
+      for (int i = 0; i < 3; ++i) r[i] = to_d2(si[i][idx]);
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const double2 d = t_apply(m, r);
+        Xout.s[m][tsite[j]] = make_double2(xt[j][m].x + d.x, xt[j][m].y + d.y);
         rm.add(d.x);
         rm.add(d.y);
       }
@@ -995,31 +996,29 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 U
   block_max_to<kIterThreads>(rm.bits(), rnext);
 }
 
-// Update pass of the last Newton iteration `fin.prev` of a batch: the final
-// update u_1 = U_3 + (T rbar)_3 (base U_3 = Uin[2], or u_0 if from_u0) if that
-// iteration met the tolerance and none before it did; nothing otherwise.
-template <bool FROM_U0, class RT>
-__global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes3 Uin,
-                                                              CPlanesOf<vec2_t<RT>> rb,
+// Final update of the last step of a batch, site by site (launch_final_update).
+__global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes3 X,
                                                               ConvCheck chk, ConvCheck fin,
-                                                              double2* u0_out, int n, Multi mu) {
+                                                              StepOut so, int n, Multi mu) {
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
   if (w.skip) return;
   offset_check(chk, w.rec);
   offset_check(fin, w.rec);
-  if (converged_at(chk) || !converged_at(fin)) return;
+  if (converged_at(chk)) return;
+  const bool at = converged_at(fin);
+  double2* const dst = offset_ptr(step_dst(so, mu, w.m), w.base);
+  if (!at && dst == L.u0) return;
   if (mu.desc != nullptr) n = L.nx * L.ny;
-  offset_planes(Uin, w.base);
-  offset_planes(rb, w.base);
-  u0_out = offset_ptr(u0_out, w.base);
+  offset_planes(X, w.base);
   const int site = w.b * kFinalSites + threadIdx.x;
   if (site >= n) return;
-  double2 r[3];
-#pragma unroll
-  for (int m = 0; m < 3; ++m) r[m] = to_d2(rb.s[m][site]);
-  const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
-  const double2 d = t_apply(2, r);
-  u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
+  double2 u = L.u0[site];
+  if (at) {
+    const double2 x = X.s[2][site];
+    u.x += x.x;
+    u.y += x.y;
+  }
+  dst[site] = u;
 }
 
 // One more block-Jacobi sweep from the iterate rin (solves with more than
@@ -1248,73 +1247,78 @@ void energy_tile(int* tx, int* ty) {
 
 namespace {
 
-// Planes3 pointers reinterpreted as stage corrections of precision RT.
-template <class RT>
-PlanesOf<vec2_t<RT>> as_r(Planes3 p) {
-  return PlanesOf<vec2_t<RT>>{{reinterpret_cast<vec2_t<RT>*>(p.s[0]),
-                               reinterpret_cast<vec2_t<RT>*>(p.s[1]),
-                               reinterpret_cast<vec2_t<RT>*>(p.s[2])}};
-}
-template <class RT>
-CPlanesOf<vec2_t<RT>> as_r(CPlanes3 p) {
-  return CPlanesOf<vec2_t<RT>>{{reinterpret_cast<const vec2_t<RT>*>(p.s[0]),
-                                reinterpret_cast<const vec2_t<RT>*>(p.s[1]),
-                                reinterpret_cast<const vec2_t<RT>*>(p.s[2])}};
-}
-
-template <int RX, int RY, bool FIRST, class RT, bool PREV = false>
+template <int RX, int RY, int MODE, class RT>
 hipError_t launch_solve_region(const Lattice& lat, CPlanes3 phib_in, Planes3 phib_out,
-                               Planes3 rout_d, unsigned long long* rslot, ConvCheck check,
+                               Planes3 out, unsigned long long* rslot, ConvCheck check,
                                FirstArgs fa, int sweeps, const Multi& mu, hipStream_t stream,
                                LaunchEvents ev, PrevStep pv = PrevStep{}) {
-  const PlanesOf<vec2_t<RT>> rout = as_r<RT>(rout_d);
   const int h = sweeps - 1, tx = RX - 2 * h, ty = RY - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
                                      : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
       block(RX * RY / 2);
   switch (sweeps) {
     case 1:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 0, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
-                 phib_out, rout, rslot, check, fa, mu, pv);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 0, MODE, RT>), grid, block, ev, lat, phib_in, phib_out,
+                 out, rslot, check, fa, mu, pv);
     case 2:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 1, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
-                 phib_out, rout, rslot, check, fa, mu, pv);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 1, MODE, RT>), grid, block, ev, lat, phib_in, phib_out,
+                 out, rslot, check, fa, mu, pv);
     case 3:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 2, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
-                 phib_out, rout, rslot, check, fa, mu, pv);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 2, MODE, RT>), grid, block, ev, lat, phib_in, phib_out,
+                 out, rslot, check, fa, mu, pv);
     case 4:
-      MB4_LAUNCH((k_stage_solve<RX, RY, 3, FIRST, RT, PREV>), grid, block, ev, lat, phib_in,
-                 phib_out, rout, rslot, check, fa, mu, pv);
+      MB4_LAUNCH((k_stage_solve<RX, RY, 3, MODE, RT>), grid, block, ev, lat, phib_in, phib_out,
+                 out, rslot, check, fa, mu, pv);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-template <int RX, int RY, bool F, class RT>
-hipError_t launch_iterate_region(const Lattice& lat, CPlanes3 Uin, Planes3 Uout,
-                                 CPlanes3 rbar_d, Planes3 rout_d, int sweeps,
+template <int RX, int RY, class RT>
+hipError_t launch_iterate_region(const Lattice& lat, CPlanes3 Xin, Planes3 Xout, int sweeps,
                                  unsigned long long* rnext, ConvCheck check, ConvCheck fin,
-                                 double2* u0_out, const Multi& mu, hipStream_t stream,
+                                 StepOut so, const Multi& mu, hipStream_t stream,
                                  LaunchEvents ev) {
-  const CPlanesOf<vec2_t<RT>> rbar = as_r<RT>(rbar_d);
-  const PlanesOf<vec2_t<RT>> rout = as_r<RT>(rout_d);
   const int h = sweeps - 1, tx = RX - 2 - 2 * h, ty = RY - 2 - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
                                      : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
       block(RX * RY / 2);
   switch (sweeps) {
     case 1:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 0, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
-                 check, fin, u0_out, mu);
+      MB4_LAUNCH((k_iterate<RX, RY, 0, RT>), grid, block, ev, lat, Xin, Xout, rnext, check, fin,
+                 so, mu);
     case 2:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 1, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
-                 check, fin, u0_out, mu);
+      MB4_LAUNCH((k_iterate<RX, RY, 1, RT>), grid, block, ev, lat, Xin, Xout, rnext, check, fin,
+                 so, mu);
     case 3:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 2, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
-                 check, fin, u0_out, mu);
+      MB4_LAUNCH((k_iterate<RX, RY, 2, RT>), grid, block, ev, lat, Xin, Xout, rnext, check, fin,
+                 so, mu);
     case 4:
-      MB4_LAUNCH((k_iterate<RX, RY, F, 3, RT>), grid, block, ev, lat, Uin, Uout, rbar, rout, rnext,
-                 check, fin, u0_out, mu);
+      MB4_LAUNCH((k_iterate<RX, RY, 3, RT>), grid, block, ev, lat, Xin, Xout, rnext, check, fin,
+                 so, mu);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE, class RT>
+hipError_t launch_first_x_region(const Lattice& lat, Planes3 xout, int sweeps,
+                                 unsigned long long* rslot, FirstArgs fa, const Multi& mu,
+                                 int region, hipStream_t stream, LaunchEvents ev, PrevStep pv) {
+  const CPlanes3 none{{nullptr, nullptr, nullptr}};
+  const Planes3 nout{{nullptr, nullptr, nullptr}};
+  const ConvCheck nochk{nullptr, 0, 0.0, false};
+  if (sizeof(RT) == sizeof(float) && region != kRegion32x32) return hipErrorInvalidValue;
+  switch (region) {
+    case kRegion32x32:
+      return launch_solve_region<32, 32, MODE, RT>(lat, none, nout, xout, rslot, nochk, fa,
+                                                   sweeps, mu, stream, ev, pv);
+    case kRegion64x16:
+      return launch_solve_region<64, 16, MODE, double>(lat, none, nout, xout, rslot, nochk, fa,
+                                                       sweeps, mu, stream, ev, pv);
+    case kRegion32x16:
+      return launch_solve_region<32, 16, MODE, double>(lat, none, nout, xout, rslot, nochk, fa,
+                                                       sweeps, mu, stream, ev, pv);
     default:
       return hipErrorInvalidValue;
   }
@@ -1326,59 +1330,35 @@ hipError_t launch_stage_solve(const Lattice& lat, CPlanes3 phib, Planes3 rout, i
                               unsigned long long* rslot, ConvCheck check, hipStream_t stream,
                               LaunchEvents ev) {
   const Planes3 none{{nullptr, nullptr, nullptr}};
-  return launch_solve_region<32, 32, false, double>(lat, phib, none, rout, rslot, check,
-                                                    FirstArgs{nullptr, false}, sweeps, Multi{},
-                                                    stream, ev);
+  return launch_solve_region<32, 32, kSolvePlain, double>(lat, phib, none, rout, rslot, check,
+                                                          FirstArgs{nullptr, false}, sweeps,
+                                                          Multi{}, stream, ev);
 }
 
 hipError_t launch_first_solve(const Lattice& lat, Planes3 rout, int sweeps,
                               unsigned long long* rslot, unsigned long long* u0max_slot,
-                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev,
-                              const Multi& mu, int region, bool fp32, const PrevStep* prev) {
+                              Planes3 phib_out, hipStream_t stream, LaunchEvents ev) {
   const CPlanes3 none{{nullptr, nullptr, nullptr}};
   const FirstArgs fa{u0max_slot, phib_out.s[0] != nullptr};
   const ConvCheck nochk{nullptr, 0, 0.0, false};
-  if (prev != nullptr && fa.store_rhs) return hipErrorInvalidValue;
-  if (fp32) {
-    if (region != kRegion32x32 || fa.store_rhs) return hipErrorInvalidValue;
-    if (prev != nullptr)
-      return launch_solve_region<32, 32, true, float, true>(lat, none, phib_out, rout, rslot,
-                                                            nochk, fa, sweeps, mu, stream, ev,
-                                                            *prev);
-    return launch_solve_region<32, 32, true, float>(lat, none, phib_out, rout, rslot, nochk, fa,
-                                                    sweeps, mu, stream, ev);
-  }
-  if (prev != nullptr) {
-    switch (region) {
-      case kRegion32x32:
-        return launch_solve_region<32, 32, true, double, true>(lat, none, phib_out, rout, rslot,
-                                                               nochk, fa, sweeps, mu, stream, ev,
-                                                               *prev);
-      case kRegion64x16:
-        return launch_solve_region<64, 16, true, double, true>(lat, none, phib_out, rout, rslot,
-                                                               nochk, fa, sweeps, mu, stream, ev,
-                                                               *prev);
-      case kRegion32x16:
-        return launch_solve_region<32, 16, true, double, true>(lat, none, phib_out, rout, rslot,
-                                                               nochk, fa, sweeps, mu, stream, ev,
-                                                               *prev);
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  switch (region) {
-    case kRegion32x32:
-      return launch_solve_region<32, 32, true, double>(lat, none, phib_out, rout, rslot, nochk, fa,
-                                               sweeps, mu, stream, ev);
-    case kRegion64x16:
-      return launch_solve_region<64, 16, true, double>(lat, none, phib_out, rout, rslot, nochk, fa,
-                                               sweeps, mu, stream, ev);
-    case kRegion32x16:
-      return launch_solve_region<32, 16, true, double>(lat, none, phib_out, rout, rslot, nochk, fa,
-                                               sweeps, mu, stream, ev);
-    default:
-      return hipErrorInvalidValue;
-  }
+  return launch_solve_region<32, 32, kSolveFirst, double>(lat, none, phib_out, rout, rslot,
+                                                          nochk, fa, sweeps, Multi{}, stream, ev);
+}
+
+hipError_t launch_first_solve_x(const Lattice& lat, Planes3 xout, int sweeps,
+                                unsigned long long* rslot, unsigned long long* u0max_slot,
+                                hipStream_t stream, LaunchEvents ev, const Multi& mu, int region,
+                                bool fp32, const PrevStep* prev) {
+  const FirstArgs fa{u0max_slot, false};
+  if (prev != nullptr)
+    return fp32 ? launch_first_x_region<kSolveFirstXPrev, float>(lat, xout, sweeps, rslot, fa, mu,
+                                                                 region, stream, ev, *prev)
+                : launch_first_x_region<kSolveFirstXPrev, double>(lat, xout, sweeps, rslot, fa,
+                                                                  mu, region, stream, ev, *prev);
+  return fp32 ? launch_first_x_region<kSolveFirstX, float>(lat, xout, sweeps, rslot, fa, mu,
+                                                           region, stream, ev, PrevStep{})
+              : launch_first_x_region<kSolveFirstX, double>(lat, xout, sweeps, rslot, fa, mu,
+                                                            region, stream, ev, PrevStep{});
 }
 
 hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, Planes3 rout,
@@ -1388,51 +1368,36 @@ hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, P
              rout, rslot, check);
 }
 
-hipError_t launch_iterate(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
-                          Planes3 rout, bool from_u0, int sweeps, unsigned long long* rnext,
-                          ConvCheck check, ConvCheck fin, double2* u0_out, hipStream_t stream,
-                          LaunchEvents ev, const Multi& mu, int region, bool fp32) {
-#define MB4_ITER_REGION(RX, RY, RT)                                                          \
-  return from_u0 ? launch_iterate_region<RX, RY, true, RT>(lat, Uin, Uout, rbar, rout,      \
-                                                           sweeps, rnext, check, fin,       \
-                                                           u0_out, mu, stream, ev)          \
-                 : launch_iterate_region<RX, RY, false, RT>(lat, Uin, Uout, rbar, rout,     \
-                                                            sweeps, rnext, check, fin,      \
-                                                            u0_out, mu, stream, ev)
+hipError_t launch_iterate(const Lattice& lat, CPlanes3 Xin, Planes3 Xout, int sweeps,
+                          unsigned long long* rnext, ConvCheck check, ConvCheck fin, StepOut so,
+                          hipStream_t stream, LaunchEvents ev, const Multi& mu, int region,
+                          bool fp32) {
   if (fp32) {
     if (region != kRegion32x32) return hipErrorInvalidValue;
-    MB4_ITER_REGION(32, 32, float);
+    return launch_iterate_region<32, 32, float>(lat, Xin, Xout, sweeps, rnext, check, fin, so,
+                                                mu, stream, ev);
   }
   switch (region) {
-    case kRegion32x32: MB4_ITER_REGION(32, 32, double);
-    case kRegion64x16: MB4_ITER_REGION(64, 16, double);
-    case kRegion32x16: MB4_ITER_REGION(32, 16, double);
-    default: return hipErrorInvalidValue;
+    case kRegion32x32:
+      return launch_iterate_region<32, 32, double>(lat, Xin, Xout, sweeps, rnext, check, fin, so,
+                                                   mu, stream, ev);
+    case kRegion64x16:
+      return launch_iterate_region<64, 16, double>(lat, Xin, Xout, sweeps, rnext, check, fin, so,
+                                                   mu, stream, ev);
+    case kRegion32x16:
+      return launch_iterate_region<32, 16, double>(lat, Xin, Xout, sweeps, rnext, check, fin, so,
+                                                   mu, stream, ev);
+    default:
+      return hipErrorInvalidValue;
   }
-#undef MB4_ITER_REGION
 }
 
-hipError_t launch_final_update(const Lattice& lat, CPlanes3 Uin, CPlanes3 rbar, bool from_u0,
-                               ConvCheck check, ConvCheck fin, double2* u0_out,
-                               hipStream_t stream, LaunchEvents ev, const Multi& mu, bool fp32) {
+hipError_t launch_final_update(const Lattice& lat, CPlanes3 X, ConvCheck check, ConvCheck fin,
+                               StepOut so, hipStream_t stream, LaunchEvents ev, const Multi& mu) {
   const int n = lat.nx * lat.ny;
   const dim3 grid(mu.desc != nullptr ? mu.blocks : (n + kFinalSites - 1) / kFinalSites),
       block(kFinalSites);
-  if (fp32) {
-    const CPlanesOf<float2> rf = as_r<float>(rbar);
-    if (from_u0)
-      MB4_LAUNCH((k_final_update<true, float>), grid, block, ev, lat, Uin, rf, check, fin, u0_out,
-                 n, mu);
-    else
-      MB4_LAUNCH((k_final_update<false, float>), grid, block, ev, lat, Uin, rf, check, fin,
-                 u0_out, n, mu);
-  }
-  if (from_u0)
-    MB4_LAUNCH((k_final_update<true, double>), grid, block, ev, lat, Uin, rbar, check, fin,
-               u0_out, n, mu);
-  else
-    MB4_LAUNCH((k_final_update<false, double>), grid, block, ev, lat, Uin, rbar, check, fin,
-               u0_out, n, mu);
+  MB4_LAUNCH(k_final_update, grid, block, ev, lat, X, check, fin, so, n, mu);
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

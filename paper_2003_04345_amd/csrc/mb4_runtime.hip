@@ -66,6 +66,27 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
+// Kernel classes for timing.  Update passes are recorded as kUpdateResidual
+// and classified when the step is decided: iteration 1 (which starts from
+// U = e_3 (x) u_0 and reads no U), later iterations, and the final update.
+enum KernelClass {
+  kFirstSolve = 0,
+  kStageSolve = 1,
+  kSweep = 2,
+  kUpdateResidualFirst = 3,
+  kUpdateResidual = 4,
+  kFinalUpdate = 5,
+  kIterateFirst = 6,
+  kIterate = 7,
+  kFinalFirst = 8,  // final update of a step fused with the next first solve
+  kFinalEnd = 9,    // recorded as such, counted as kFinalUpdate
+};
+constexpr int kKernelClasses = 9;
+const char* const kKernelNames[kKernelClasses] = {
+    "stage_solve_first", "stage_solve", "stage_sweep", "update_residual_first",
+    "update_residual",   "final_update", "iterate_first", "iterate",
+    "final_first"};
+
 }  // namespace
 
 struct mb4_state {
@@ -96,6 +117,7 @@ struct mb4_state {
   std::vector<void*> host_allocs;
   double* V = nullptr;
   double2* u0 = nullptr;
+  double2* u0b = nullptr;  // second u_0 buffer of the fused path's batches
   double2* Ua[3] = {nullptr, nullptr, nullptr};
   double2* Ub[3] = {nullptr, nullptr, nullptr};
   double2* phib[3] = {nullptr, nullptr, nullptr};
@@ -124,8 +146,8 @@ struct mb4_state {
     hipEvent_t a, b;
   };
   std::vector<Rec> prof_pending;
-  int64_t prof_launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t prof_launches[kKernelClasses] = {};
+  double prof_ms[kKernelClasses] = {};
   int64_t steps_done = 0;
   int last_iters = 0;
   int last_sweeps = 0;
@@ -142,11 +164,12 @@ ConvCheck conv_check(const mb4_state* s, const unsigned long long* rec, int prev
   return ConvCheck{rec, prev, s->eps, s->relative_eps};
 }
 
-// Device bytes of a state: V (8 B/site), u_0 (16), two stage-value fields
-// (2 x 48), the transformed residual (48), two stage-correction fields
-// (2 x 48); plus the statistics records and the energy partial sums.
+// Device bytes of a state: V (8 B/site), two u_0 buffers (2 x 16), two
+// stage-value fields (2 x 48), the transformed residual (48), two
+// stage-correction fields (2 x 48); plus the statistics records and the
+// energy partial sums.
 size_t footprint_bytes(size_t sites, int nx, int ny, int max_newton) {
-  return sites * 264 + size_t(kBatch + 1) * size_t(max_newton + 1) * 8 +
+  return sites * 280 + size_t(kBatch + 1) * size_t(max_newton + 1) * 8 +
          mb4::energy_partials_count(nx, ny) * sizeof(double) + 8 * sizeof(double);
 }
 
@@ -218,27 +241,6 @@ int use_device(const mb4_state* s) {
   HIP_TRY(hipSetDevice(s->device));
   return MB4_OK;
 }
-
-// Kernel classes for timing.  Update passes are recorded as kUpdateResidual
-// and classified when the step is decided: iteration 1 (which starts from
-// U = e_3 (x) u_0 and reads no U), later iterations, and the final update.
-enum KernelClass {
-  kFirstSolve = 0,
-  kStageSolve = 1,
-  kSweep = 2,
-  kUpdateResidualFirst = 3,
-  kUpdateResidual = 4,
-  kFinalUpdate = 5,
-  kIterateFirst = 6,
-  kIterate = 7,
-  kFinalFirst = 8,  // final update of a step fused with the next first solve
-  kFinalEnd = 9,    // recorded as such, counted as kFinalUpdate
-};
-constexpr int kKernelClasses = 9;
-const char* const kKernelNames[kKernelClasses] = {
-    "stage_solve_first", "stage_solve", "stage_sweep", "update_residual_first",
-    "update_residual",   "final_update", "iterate_first", "iterate",
-    "final_first"};
 
 int prof_event(mb4_state* s, hipEvent_t* ev) {
   if (s->ev_used == s->ev_pool.size()) {
@@ -334,74 +336,75 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
   return MB4_OK;
 }
 
-// Newton iterate U^j lives in Ua (j odd) or Ub (j even); the stage solution
-// rbar^l of iteration l in ra (l odd) or rb (l even) on the fused path.
-double2* const* u_planes(mb4_state* s, int j) { return (j % 2 == 1) ? s->Ua : s->Ub; }
-double2* const* r_planes(mb4_state* s, int l) { return (l & 1) ? s->ra : s->rb; }
 CPlanes3 cp(double2* const* a) { return CPlanes3{{a[0], a[1], a[2]}}; }
 Planes3 pp(double2* const* a) { return Planes3{{a[0], a[1], a[2]}}; }
 
-// Fused path (at most four sweeps): iteration l's stage solve is enqueued as
-// part of the pass that updates iteration l - 1 (k_iterate), iteration 1's by
-// the first-solve kernel; after iteration `last` a final-update pass writes
-// u_1 over u_0 if `last` is where the step converged.  Within a batch, the
-// final update of step k - 1 is fused into the first solve of step k
-// (prev_rec: step k - 1's record; emit_final = false for a step whose
-// successor takes its final update), and the stage-correction buffers
-// alternate with sigma = k * iters so that the first solve of step k does
-// not write the buffer step k - 1's final update reads.
-int enqueue_iterations_fused(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
+// Fused path (at most four sweeps): the iterate of Newton iteration l is
+// X^l = U^l - e (x) u_0 (see mb4::StepOut), in Ua (l + sigma odd) or Ub.
+// Iteration 1's stage solve is the first-solve kernel, iteration l's (l >= 2)
+// is part of the pass that forms the residual of iteration l - 1
+// (k_iterate), and a step's u_1 is written by the pass after the iteration
+// that met the tolerance.
+//
+// Batch step k of `count` reads u_0 from u0 (k even) or u0b (k odd) and
+// writes u_1 to the other buffer, the last step to u0, so that a batch ends
+// where it started.  The final update of step k - 1 is fused into the first
+// solve of step k (prev_rec: step k - 1's record); only the last step has a
+// final-update pass of its own (emit_final).  sigma = k * iters alternates the
+// X buffers so that the first solve of step k does not write the X that step
+// k - 1's final update reads.
+double2* const* x_planes(mb4_state* s, int l) { return (l & 1) ? s->Ua : s->Ub; }
+double2* batch_u0(mb4_state* s, int k) { return (k & 1) ? s->u0b : s->u0; }
+
+int enqueue_iterations_fused(mb4_state* s, int step, int count, unsigned long long* rec,
                              int first, int last, int sigma = 0,
                              const unsigned long long* prev_rec = nullptr,
                              bool emit_final = true) {
-  auto rp = [&](int l) { return r_planes(s, l + sigma); };
+  Lattice L = lattice_of(s);
+  double2* const src = batch_u0(s, step);
+  L.u0 = src;
+  const mb4::StepOut so{step == count - 1 ? s->u0 : batch_u0(s, step + 1), s->u0};
+  const ConvCheck none{nullptr, 0, 0.0, false};
+  auto xp = [&](int l) { return x_planes(s, l + sigma); };
   for (int l = first; l <= last; ++l) {
     if (l == 1) {
+      unsigned long long* const u0max = s->relative_eps ? rec : nullptr;
       if (prev_rec != nullptr) {
         // Step k - 1 ran `last` iterations too, with sigma_{k-1} = sigma - last
-        // (mod 2), so its rbar^last sits in r_planes(last + sigma_{k-1}).
+        // (mod 2), so its X^last sits in x_planes(last + sigma_{k-1}).
         const int sigma_prev = (sigma + last) & 1;
-        const mb4::PrevStep pv{cp(u_planes(s, last - 1)), cp(r_planes(s, last + sigma_prev)),
-                               conv_check(s, prev_rec, last - 1), conv_check(s, prev_rec, last),
-                               s->u0};
+        const mb4::PrevStep pv{batch_u0(s, step - 1), cp(x_planes(s, last + sigma_prev)),
+                               last >= 2 ? conv_check(s, prev_rec, last - 1) : none,
+                               conv_check(s, prev_rec, last), src, s->u0};
         LAUNCH(s, kFinalFirst, step, 1,
-               mb4::launch_first_solve(L, pp(rp(1)), s->sweeps, rec + 1,
-                                       s->relative_eps ? rec : nullptr,
-                                       Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_,
-                                       mb4::Multi{}, mb4::kRegion32x32, s->fp32, &pv));
+               mb4::launch_first_solve_x(L, pp(xp(1)), s->sweeps, rec + 1, u0max, s->q, ev_,
+                                         mb4::Multi{}, mb4::kRegion32x32, s->fp32, &pv));
       } else {
         LAUNCH(s, kFirstSolve, step, 1,
-               mb4::launch_first_solve(L, pp(rp(1)), s->sweeps, rec + 1,
-                                       s->relative_eps ? rec : nullptr,
-                                       Planes3{{nullptr, nullptr, nullptr}}, s->q, ev_,
-                                       mb4::Multi{}, mb4::kRegion32x32, s->fp32));
+               mb4::launch_first_solve_x(L, pp(xp(1)), s->sweeps, rec + 1, u0max, s->q, ev_,
+                                         mb4::Multi{}, mb4::kRegion32x32, s->fp32, nullptr));
       }
       continue;
     }
-    const int j = l - 1;  // the iteration this pass updates
-    const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
-    const ConvCheck fin = conv_check(s, rec, j);
-    const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
+    const int j = l - 1;  // the iteration whose residual this pass forms
+    const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : none;
     LAUNCH(s, kIterate, step, j,
-           mb4::launch_iterate(L, uin, pp(u_planes(s, j)), cp(rp(j)), pp(rp(l)), j == 1,
-                               s->sweeps, rec + l, chk, fin, s->u0, s->q, ev_, mb4::Multi{},
+           mb4::launch_iterate(L, cp(xp(j)), pp(xp(l)), s->sweeps, rec + l, chk,
+                               conv_check(s, rec, j), so, s->q, ev_, mb4::Multi{},
                                mb4::kRegion32x32, s->fp32));
   }
   if (!emit_final) return MB4_OK;
-  const int j = last;
-  const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : ConvCheck{nullptr, 0, 0.0, false};
-  const ConvCheck fin = conv_check(s, rec, j);
-  const CPlanes3 uin = j >= 2 ? cp(u_planes(s, j - 1)) : CPlanes3{{nullptr, nullptr, nullptr}};
-  LAUNCH(s, kFinalEnd, step, j,
-         mb4::launch_final_update(L, uin, cp(rp(j)), j == 1, chk, fin, s->u0, s->q, ev_,
-                                  mb4::Multi{}, s->fp32));
+  const ConvCheck chk = last >= 2 ? conv_check(s, rec, last - 1) : none;
+  LAUNCH(s, kFinalEnd, step, last,
+         mb4::launch_final_update(L, cp(xp(last)), chk, conv_check(s, rec, last), so, s->q, ev_));
   return MB4_OK;
 }
 
+// Iterations first .. last of a single step (u_0 and u_1 in s->u0).
 int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
                        int first, int last) {
   if (s->sweeps <= mb4::kMaxFusedSweeps)
-    return enqueue_iterations_fused(s, L, step, rec, first, last);
+    return enqueue_iterations_fused(s, 0, 1, rec, first, last);
   for (int l = first; l <= last; ++l) {
     double2* const* rfin = nullptr;
     const int rc = enqueue_solve(s, L, step, l, rec, &rfin);
@@ -473,15 +476,13 @@ void update_prediction(mb4_state* s, int batch_max) {
 int enqueue_batch(mb4_state* s, int count, int iters) {
   const Lattice L = lattice_of(s);
   HIP_TRY(mb4::launch_clear(s->ring, count * s->rec_len, s->q));
-  // A step of one iteration has u_0 as the base of its final update, which
-  // the fused kernel overwrites block by block, so only iters >= 2 fuses.
-  const bool fuse = s->sweeps <= mb4::kMaxFusedSweeps && iters >= 2;
+  const bool fused = s->sweeps <= mb4::kMaxFusedSweeps;
   for (int k = 0; k < count; ++k) {
     unsigned long long* rec = s->ring + size_t(k) * s->rec_len;
     const int rc =
-        fuse ? enqueue_iterations_fused(s, L, k, rec, 1, iters, (k * iters) % 2,
-                                        k > 0 ? rec - s->rec_len : nullptr, k == count - 1)
-             : enqueue_iterations(s, L, k, rec, 1, iters);
+        fused ? enqueue_iterations_fused(s, k, count, rec, 1, iters, (k * iters) & 1,
+                                         k > 0 ? rec - s->rec_len : nullptr, k == count - 1)
+              : enqueue_iterations(s, L, k, rec, 1, iters);
     if (rc != MB4_OK) return rc;
   }
   return MB4_OK;
@@ -692,6 +693,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   };
   if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->V), s->sites * sizeof(double));
   alloc_field(&s->u0);
+  alloc_field(&s->u0b);
   for (int i = 0; i < 3; ++i) {
     alloc_field(&s->Ua[i]);
     alloc_field(&s->Ub[i]);

@@ -181,7 +181,7 @@ int mb4_server_create(uint64_t arena_bytes, int32_t max_active, int32_t batch_st
   // member sites (energy partial sums: 1/256 of a site's share).
   const size_t fixed = size_t(kMaxBatchSteps) * max_active * (o.max_newton + 1) * 8 +
                        size_t(max_active) * 120 + (size_t(1) << 20);
-  const size_t per_site = eng::bytes_per_site(fp32) + 1;
+  const size_t per_site = eng::bytes_per_site() + 1;
   if (arena_bytes <= fixed || (arena_bytes - fixed) / per_site < 9)
     return fail(MB4_EINVAL, "arena_bytes too small");
   const size_t capacity = std::min<size_t>((arena_bytes - fixed) / per_site, size_t(INT32_MAX));

@@ -277,7 +277,7 @@ def test_ensemble_create_rejects_invalid_options(lib, field, value):
 
 def test_ensemble_memory_budget_is_enforced_before_allocation(lib):
     opt = M.mb4_options_default()
-    opt.mem_budget = 4096   # below 216 bytes/site * 128 sites
+    opt.mem_budget = 4096   # below 136 bytes/site * 128 sites
     rc, out = _ens_create(lib, opt=opt)
     assert rc == M.MB4_ENOMEM
     assert out.value is None

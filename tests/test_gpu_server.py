@@ -84,7 +84,7 @@ def test_admission_respects_the_arena():
              for i in range(4)]
     mix = [x for pair in zip(big, small) for x in pair]
     inputs = [L.make_inputs(cfg) for cfg, _ in mix]
-    per_site = 216
+    per_site = 136
     arena = 5000 * per_site + 32 * 16 * 51 * 8 + 16 * 120 + (1 << 20)
     with M.MB4Server(arena, max_active=16, batch_steps=4) as srv:
         cap = srv.stats()["capacity_sites"]
@@ -137,6 +137,8 @@ def test_request_too_large_is_rejected_at_submission():
     torch_cuda()
     cfg = L.config("lattice32", nx=128, ny=128, defect_count=10, sigma=8.0)
     v, p, q = L.make_inputs(cfg)
-    with M.MB4Server(1 << 22, max_active=2, batch_steps=4) as srv:
+    # 2 MiB: about 7,400 sites after the step records, below 128^2.
+    with M.MB4Server(1 << 21, max_active=2, batch_steps=4) as srv:
+        assert srv.stats()["capacity_sites"] < cfg.nx * cfg.ny
         with pytest.raises(M.Mb4Error):
             srv.submit(cfg, v, p, q, 5)
