@@ -119,7 +119,9 @@ __device__ __forceinline__ double conv_tol(double eps, double u0max) {
   return eps * (u0max > DBL_MIN ? u0max : DBL_MIN);
 }
 
-// True when Newton iteration c.prev (>= 1) already met the tolerance.
+// True when Newton iteration c.prev (>= 1) already met the tolerance.  The
+// record is read with a scalar load (it is not written while a kernel that
+// tests it runs), which later blocks on a CU find in the scalar cache.
 __device__ __forceinline__ bool converged_at(const ConvCheck& c) {
   if (c.rec == nullptr) return false;
   const double r = bits_double(c.rec[c.prev]);
@@ -182,7 +184,8 @@ __device__ __forceinline__ T* offset_ptr(T* p, long long n) {
 // serialise across the XCDs; most blocks hold a value below the running
 // maximum, so thread 0 reads it first (a coherent load) and only posts a
 // larger value.  The slot only grows, so a block that skips has v <= what
-// the slot already holds.
+// the slot already holds.  (Reading the slot earlier, when the block starts,
+// lets more blocks post and is slower.)
 template <int NT>
 __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long* slot) {
   constexpr int kW = NT / 64;
@@ -780,11 +783,12 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
   if (w.skip) return;
   offset_check(chk, w.rec);
-  if (converged_at(chk)) return;
   offset_check(fin, w.rec);
+  rnext = offset_ptr(rnext, w.rec);
+  if (converged_at(chk)) return;
+  const bool at = converged_at(fin);
   offset_planes(Xin, w.base);
   offset_planes(Xout, w.base);
-  rnext = offset_ptr(rnext, w.rec);
   constexpr int RN = RX * RY;
   constexpr int TSX = RX - 2 - 2 * H, TSY = RY - 2 - 2 * H;
   constexpr int PER = RN / kIterThreads;
@@ -796,7 +800,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
   const int ox = tx0 - H - 1, oy = ty0 - H - 1;  // region origin
   const bool fast = nx >= RX + 2 && ny >= RY + 2;
 
-  if (converged_at(fin)) {
+  if (at) {
     // Final update on this block's tile only.
     double2* const dst = offset_ptr(step_dst(so, mu, w.m), w.base);
 #pragma unroll
@@ -813,8 +817,16 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
     return;
   }
 
-  // W_i (FP64), then the stage iterates (RT) in the same LDS.
+  // W_i (FP64), then the stage iterates (RT) in the same LDS.  X^iter of
+  // the tile is kept in LDS too when both fit this block's share of the
+  // CU's 160 KiB at the occupancy of the launch bounds (4 waves per SIMD);
+  // otherwise it is read again at the end.  Holding it in registers through
+  // the sweeps would spill.
+  constexpr int TN = TSX * TSY;
+  constexpr int kLdsShare = 160 * 1024 * (kIterThreads / 64) / (4 * 4);
+  constexpr bool XLDS = RN * 48 + TN * 48 + 64 <= kLdsShare;
   __shared__ double2 sb[3][RN];
+  __shared__ double2 sx[3][XLDS ? TN : 1];
   R2(*const si)[RN] = reinterpret_cast<R2(*)[RN]>(&sb[0][0]);
   int gsite[PER];
   double2 u0v[PER];
@@ -836,6 +848,13 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
+    if (XLDS) {
+      const int tx = idx % RX - (H + 1), ty = idx / RX - (H + 1);
+      if (tx >= 0 && tx < TSX && ty >= 0 && ty < TSY) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) sx[i][ty * TSX + tx] = xv[j][i];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       sb[i][idx] = make_double2(MB4_C[i] * u0v[j].x + MB4_E[i][0] * xv[j][0].x +
@@ -947,8 +966,6 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
       }
     }
   }
-  // X^iter of the tile again (its first read is likely still in L2): holding
-  // it in registers through the sweeps would spill.
   // Tile positions never wrap, so their site is formed afresh here (reusing
   // the phase-1 addresses would keep them live, and spilled, all along).
   int tsite[PER];
@@ -960,7 +977,7 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
     const bool tile = lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY &&
                       ox + lx < nx && oy + ly < ny;
     tsite[j] = tile ? (oy + ly) * nx + (ox + lx) : -1;
-    if (tile) {
+    if (tile && !XLDS) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) xt[j][m] = Xin.s[m][tsite[j]];
     }
@@ -981,6 +998,11 @@ __global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 X
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
     if (tsite[j] >= 0) {
+      if (XLDS) {
+        const int tp = (idx / RX - (H + 1)) * TSX + (idx % RX - (H + 1));
+#pragma unroll
+        for (int m = 0; m < 3; ++m) xt[j][m] = sx[m][tp];
+      }
       double2 r[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) r[i] = to_d2(si[i][idx]);
