@@ -9,11 +9,12 @@
 //   the tolerance writes u_1 = U_{c_3} over u_0 (Sec. 2.2, last paragraph:
 //   c_3 = 1); the others apply the Newton update and form the next residual.
 //   Every kernel of iteration l >= 2 returns at once when ||r^{l-1}||_inf
-//   already met the tolerance.  Since u_0 is updated in place and no buffer
-//   moves, up to kBatch steps are enqueued back to back with the previous
-//   step's iteration count, and one read-back of their statistics per batch
-//   tells the host where each converged (see run_batch for the rare step
-//   that needs more iterations).
+//   already met the tolerance.  Since the buffers a step uses depend only on
+//   its place in the batch (u_0 alternates between two buffers and returns
+//   to the first at the batch's end), up to kBatch steps are enqueued back to
+//   back with the previous step's iteration count, and one read-back of
+//   their statistics per batch tells the host where each converged (see
+//   run_batch for the rare step that needs more iterations).
 #include <float.h>
 #include <math.h>
 #include <stdarg.h>
