@@ -135,7 +135,7 @@ def step_bytes_per_site(iters: int) -> int:
 
 def run_ensemble(args, torch, M) -> int:
     """The disorder ensemble: args.members realisations of 128^2 advanced
-    together by mb4_ensemble_step, after the region autotuner."""
+    together by mb4_ensemble_step, after the region/sweeps autotuner."""
     members = L.ensemble(args.members)
     inputs = [L.make_inputs(m) for m in members]
     steps = args.steps if args.steps is not None else L.ENSEMBLE_STEPS
@@ -146,10 +146,10 @@ def run_ensemble(args, torch, M) -> int:
     h_start = ens.energies()
     tuning = None
     if args.tune_steps > 0:
-        best, ms = ens.tune(args.tune_steps)
-        tuning = {"region": M.REGION_NAMES[best],
-                  "ms_per_step": {M.REGION_NAMES[r]: (t if t >= 0 else None)
-                                  for r, t in enumerate(ms)}}
+        region, sweeps, ms = ens.tune_all(args.tune_steps)
+        tuning = {"region": M.REGION_NAMES[region], "inner_sweeps": sweeps,
+                  "ms_per_step": {f"{M.REGION_NAMES[r]}/{sw}": t
+                                  for (r, sw), t in sorted(ms.items())}}
     if args.warmup:
         if ens.step(args.warmup) != M.MB4_OK:
             raise RuntimeError(f"warmup failed: {M.error_detail()}")
@@ -353,7 +353,7 @@ def main(argv=None) -> int:
     ap.add_argument("--members", type=int, default=L.ENSEMBLE_SIZE,
                     help="ensemble128: number of realisations")
     ap.add_argument("--tune-steps", type=int, default=32,
-                    help="ensemble128: steps the region autotuner times per shape (0: no tuning)")
+                    help="ensemble128: steps the autotuner times per region/sweeps pair (0: no tuning)")
     ap.add_argument("--eps", type=float, default=0.0, help="Newton tolerance (0: library default)")
     ap.add_argument("--sweeps", type=int, default=0, help="block-Jacobi sweeps (0: default)")
     ap.add_argument("--fp32-solve", action="store_true",

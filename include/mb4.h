@@ -288,6 +288,23 @@ MB4_API int32_t mb4_ensemble_region(const mb4_ensemble* ens);
 MB4_API int mb4_ensemble_tune(mb4_ensemble* ens, int32_t steps, int32_t* best,
                               double* ms_per_step);
 
+/* Block-Jacobi sweeps per stage solve of every member (1 .. 4; the stage
+ * solves, Eq. MB4_5, are inexact inner solves of the simplified Newton
+ * iteration, so the count changes the number of Newton iterations, not the
+ * root).  mb4_ensemble_sweeps returns it (-1 for NULL).
+ * Errors: MB4_EINVAL (out of range, or the region leaves no tile). */
+MB4_API int mb4_ensemble_set_sweeps(mb4_ensemble* ens, int32_t sweeps);
+MB4_API int32_t mb4_ensemble_sweeps(const mb4_ensemble* ens);
+
+/* Autotuner over region shape and sweeps together: as mb4_ensemble_tune,
+ * for every shape and 2 .. 4 sweeps, keeping the fastest pair (fewer sweeps
+ * cost less per Newton iteration but may need more iterations).
+ * ms_per_step (may be NULL) receives 4 * MB4_REGION_COUNT times, index
+ * (sweeps - 1) * MB4_REGION_COUNT + region, negative for a pair not tried;
+ * *best_region and *best_sweeps (either may be NULL) the pair kept. */
+MB4_API int mb4_ensemble_tune_all(mb4_ensemble* ens, int32_t steps, int32_t* best_region,
+                                  int32_t* best_sweeps, double* ms_per_step);
+
 /* ------------------------------------------------------------------------
  * Serving: solve requests of different lattice sizes and step counts on one
  * GPU with continuous batching.  Requests wait in a FIFO queue and are

@@ -65,6 +65,10 @@ int energy_of(Engine* e, const MemberDesc& d, double out[6]);
 int set_region(Engine* e, int region);
 int region(const Engine* e);
 bool region_usable(const Engine* e, int region);
+// Block-Jacobi sweeps per stage solve (1 .. kMaxFusedSweeps); the current
+// region must leave a tile at the new count.
+int set_sweeps(Engine* e, int sweeps);
+int sweeps(const Engine* e);
 
 // u_0 of the whole capacity to / from a device buffer (autotuning trials).
 int save_u0(Engine* e, void* dst);

@@ -545,6 +545,31 @@ int set_region(Engine* e, int r) {
 
 int region(const Engine* e) { return e->region; }
 
+int set_sweeps(Engine* e, int sweeps) {
+  if (sweeps < 1 || sweeps > kMaxFusedSweeps)
+    return fail(MB4_EINVAL, "sweeps must be in [1, %d]", kMaxFusedSweeps);
+  if (sweeps == e->cfg.sweeps) return MB4_OK;
+  HIP_TRY(hipSetDevice(e->device));
+  HIP_TRY(hipStreamSynchronize(e->cfg.stream));
+  const int old = e->cfg.sweeps;
+  e->cfg.sweeps = sweeps;
+  if (!region_usable(e, e->region)) {
+    e->cfg.sweeps = old;
+    return fail(MB4_EINVAL, "region %s leaves no tile at %d sweeps", region_name(e->region),
+                sweeps);
+  }
+  const int rc = upload_blocks(e);
+  if (rc != MB4_OK) {
+    e->cfg.sweeps = old;
+    (void)upload_blocks(e);
+    return rc;
+  }
+  drop_graphs(e);
+  return MB4_OK;
+}
+
+int sweeps(const Engine* e) { return e->cfg.sweeps; }
+
 size_t u0_bytes(const Engine* e) { return sizeof(double2) * e->cfg.capacity; }
 
 int save_u0(Engine* e, void* dst) {

@@ -58,6 +58,100 @@ size_t footprint_bytes(size_t total, int count, int max_newton) {
          size_t(count) * 120 + total / 256 * 12 * sizeof(double);
 }
 
+// A launch configuration the autotuner tries.
+struct Shape {
+  int region = mb4::kRegion32x32;
+  int sweeps = 3;
+};
+
+// Times `steps` steps of the ensemble under each shape (one untimed pass
+// first: graph capture, caches, the iteration prediction), restoring every
+// member's state and counters after each trial.  times[k] receives ms per
+// step of shapes[k], or -1 where the shape leaves no tile, is not built
+// (FP32 solves: 32 x 32 only) or has fewer than min_sweeps sweeps.  The
+// fastest shape is selected, with the iteration prediction its trial
+// learnt; on an error the original shape and prediction come back.
+int tune_shapes(mb4_ensemble* e, int32_t steps, const std::vector<Shape>& shapes,
+                std::vector<double>* times, Shape* chosen, int min_sweeps = 1) {
+  eng::Engine* g = e->engine;
+  const hipStream_t s = eng::stream(g);
+  void* backup = nullptr;
+  hipError_t err = hipMalloc(&backup, eng::u0_bytes(g));
+  if (err != hipSuccess) return fail(MB4_ENOMEM, "tune backup: %s", hipGetErrorString(err));
+  const std::vector<int64_t> done0 = e->steps_done;
+  const std::vector<int> iters0 = e->last_iters;
+  const Shape shape0{eng::region(g), eng::sweeps(g)};
+  const int pred0 = eng::iteration_prediction(g);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  times->assign(shapes.size(), -1.0);
+  *chosen = shape0;
+  int pred_best = pred0;
+  double best_ms = -1.0;
+  auto restore = [&]() {
+    e->steps_done = done0;
+    e->last_iters = iters0;
+    return eng::restore_u0(g, backup);
+  };
+  auto select = [&](const Shape& sh) {
+    // Sweeps first when they shrink (the tile grows), region first otherwise.
+    int rc = MB4_OK;
+    if (sh.sweeps < eng::sweeps(g)) {
+      rc = eng::set_sweeps(g, sh.sweeps);
+      if (rc == MB4_OK) rc = eng::set_region(g, sh.region);
+    } else {
+      rc = eng::set_region(g, sh.region);
+      if (rc == MB4_OK) rc = eng::set_sweeps(g, sh.sweeps);
+    }
+    return rc;
+  };
+  int rc = eng::save_u0(g, backup);
+  if (rc == MB4_OK && ((err = hipEventCreate(&t0)) != hipSuccess ||
+                       (err = hipEventCreate(&t1)) != hipSuccess))
+    rc = fail(MB4_EDEVICE, "tune events: %s", hipGetErrorString(err));
+  for (size_t k = 0; k < shapes.size() && rc == MB4_OK; ++k) {
+    const Shape& sh = shapes[k];
+    if (sh.sweeps < min_sweeps) continue;
+    // Usable: the region exists in this precision and leaves a tile at these
+    // sweeps (checked by selecting it; a refusal only skips the shape).
+    if (select(sh) != MB4_OK) {
+      rc = select(shape0);
+      continue;
+    }
+    eng::set_iteration_prediction(g, pred0);
+    // One untimed pass (graph capture, caches), then the timed one.
+    rc = mb4_ensemble_step(e, std::min<int64_t>(steps, kBatch));
+    if (rc == MB4_OK) rc = restore();
+    if (rc == MB4_OK && (err = hipEventRecord(t0, s)) != hipSuccess)
+      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+    if (rc == MB4_OK) rc = mb4_ensemble_step(e, steps);
+    if (rc == MB4_OK && (err = hipEventRecord(t1, s)) != hipSuccess)
+      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+    if (rc == MB4_OK && (err = hipEventSynchronize(t1)) != hipSuccess)
+      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+    float ms = 0.0f;
+    if (rc == MB4_OK && (err = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+    const int pred = eng::iteration_prediction(g);
+    if (rc == MB4_OK) rc = restore();
+    if (rc == MB4_OK) {
+      (*times)[k] = double(ms) / steps;
+      if (best_ms < 0.0 || (*times)[k] < best_ms) {
+        best_ms = (*times)[k];
+        *chosen = sh;
+        pred_best = pred;
+      }
+    }
+  }
+  const int rc_sel = select(rc == MB4_OK ? *chosen : shape0);
+  if (rc != MB4_OK) (void)restore();
+  eng::set_iteration_prediction(g, rc == MB4_OK ? pred_best : pred0);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(backup);
+  if (rc != MB4_OK) return rc;
+  return rc_sel;
+}
+
 }  // namespace
 
 extern "C" {
@@ -239,71 +333,49 @@ int32_t mb4_ensemble_region(const mb4_ensemble* e) {
   return e == nullptr ? -1 : eng::region(e->engine);
 }
 
+int mb4_ensemble_set_sweeps(mb4_ensemble* e, int32_t sweeps) {
+  const int rc = check(e);
+  if (rc != MB4_OK) return rc;
+  return eng::set_sweeps(e->engine, sweeps);
+}
+
+int32_t mb4_ensemble_sweeps(const mb4_ensemble* e) {
+  return e == nullptr ? -1 : eng::sweeps(e->engine);
+}
+
 int mb4_ensemble_tune(mb4_ensemble* e, int32_t steps, int32_t* best, double* ms_per_step) {
   int rc = check(e);
   if (rc != MB4_OK) return rc;
   if (steps < 1) return fail(MB4_EINVAL, "steps must be >= 1");
-  eng::Engine* g = e->engine;
-  const hipStream_t s = eng::stream(g);
-  void* backup = nullptr;
-  hipError_t err = hipMalloc(&backup, eng::u0_bytes(g));
-  if (err != hipSuccess) return fail(MB4_ENOMEM, "tune backup: %s", hipGetErrorString(err));
-  const std::vector<int64_t> done0 = e->steps_done;
-  const std::vector<int> iters0 = e->last_iters;
-  const int pred0 = eng::iteration_prediction(g), region0 = eng::region(g);
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  double times[mb4::kRegionCount];
-  int chosen = region0;
-  double best_ms = -1.0;
-  // Member states and counters go back after every trial; the iteration
-  // prediction learnt in the untimed pass is kept for the timed one and
-  // reset at the end.
-  auto restore = [&]() {
-    e->steps_done = done0;
-    e->last_iters = iters0;
-    return eng::restore_u0(g, backup);
-  };
-  rc = eng::save_u0(g, backup);
-  if (rc == MB4_OK && ((err = hipEventCreate(&t0)) != hipSuccess ||
-                       (err = hipEventCreate(&t1)) != hipSuccess))
-    rc = fail(MB4_EDEVICE, "tune events: %s", hipGetErrorString(err));
-  for (int r = 0; r < mb4::kRegionCount && rc == MB4_OK; ++r) {
-    times[r] = -1.0;
-    if (!eng::region_usable(g, r)) continue;
-    rc = eng::set_region(g, r);
-    // One untimed pass (graph capture, caches), then the timed one.
-    if (rc == MB4_OK) rc = mb4_ensemble_step(e, std::min<int64_t>(steps, kBatch));
-    if (rc == MB4_OK) rc = restore();
-    if (rc == MB4_OK && (err = hipEventRecord(t0, s)) != hipSuccess)
-      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
-    if (rc == MB4_OK) rc = mb4_ensemble_step(e, steps);
-    if (rc == MB4_OK && (err = hipEventRecord(t1, s)) != hipSuccess)
-      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
-    if (rc == MB4_OK && (err = hipEventSynchronize(t1)) != hipSuccess)
-      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
-    float ms = 0.0f;
-    if (rc == MB4_OK && (err = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
-      rc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
-    if (rc == MB4_OK) rc = restore();
-    if (rc == MB4_OK) {
-      times[r] = double(ms) / steps;
-      if (best_ms < 0.0 || times[r] < best_ms) {
-        best_ms = times[r];
-        chosen = r;
-      }
-    }
-  }
-  const int rc_sel = eng::set_region(g, rc == MB4_OK ? chosen : region0);
-  if (rc != MB4_OK) (void)restore();
-  eng::set_iteration_prediction(g, pred0);
-  if (t0) (void)hipEventDestroy(t0);
-  if (t1) (void)hipEventDestroy(t1);
-  (void)hipFree(backup);
+  const int sw = eng::sweeps(e->engine);
+  std::vector<Shape> shapes;
+  for (int r = 0; r < mb4::kRegionCount; ++r) shapes.push_back(Shape{r, sw});
+  std::vector<double> times;
+  Shape chosen{};
+  rc = tune_shapes(e, steps, shapes, &times, &chosen);
   if (rc != MB4_OK) return rc;
-  if (rc_sel != MB4_OK) return rc_sel;
-  if (best) *best = chosen;
+  if (best) *best = chosen.region;
   if (ms_per_step)
-    for (int r = 0; r < mb4::kRegionCount; ++r) ms_per_step[r] = times[r];
+    for (int r = 0; r < mb4::kRegionCount; ++r) ms_per_step[r] = times[size_t(r)];
+  return MB4_OK;
+}
+
+int mb4_ensemble_tune_all(mb4_ensemble* e, int32_t steps, int32_t* best_region,
+                          int32_t* best_sweeps, double* ms_per_step) {
+  int rc = check(e);
+  if (rc != MB4_OK) return rc;
+  if (steps < 1) return fail(MB4_EINVAL, "steps must be >= 1");
+  std::vector<Shape> shapes;
+  for (int sw = 1; sw <= mb4::kMaxFusedSweeps; ++sw)
+    for (int r = 0; r < mb4::kRegionCount; ++r) shapes.push_back(Shape{r, sw});
+  std::vector<double> times;
+  Shape chosen{};
+  rc = tune_shapes(e, steps, shapes, &times, &chosen, /*min_sweeps=*/2);
+  if (rc != MB4_OK) return rc;
+  if (best_region) *best_region = chosen.region;
+  if (best_sweeps) *best_sweeps = chosen.sweeps;
+  if (ms_per_step)
+    for (size_t k = 0; k < times.size(); ++k) ms_per_step[k] = times[k];
   return MB4_OK;
 }
 

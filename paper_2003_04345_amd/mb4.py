@@ -108,6 +108,10 @@ _SIGNATURES = {
     "mb4_ensemble_set_region": (c_int, [c_void_p, c_int32]),
     "mb4_ensemble_region": (c_int32, [c_void_p]),
     "mb4_ensemble_tune": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_double)]),
+    "mb4_ensemble_set_sweeps": (c_int, [c_void_p, c_int32]),
+    "mb4_ensemble_sweeps": (c_int32, [c_void_p]),
+    "mb4_ensemble_tune_all": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                      POINTER(c_double)]),
     "mb4_server_create": (c_int, [c_uint64, c_int32, c_int32, POINTER(mb4_options),
                                   POINTER(c_void_p)]),
     "mb4_server_destroy": (None, [c_void_p]),
@@ -488,6 +492,27 @@ class MB4Ensemble:
         _check(load_library().mb4_ensemble_tune(self._e, int(steps), byref(best), ms),
                "mb4_ensemble_tune")
         return best.value, list(ms)
+
+    def set_sweeps(self, sweeps: int) -> None:
+        _check(load_library().mb4_ensemble_set_sweeps(self._e, int(sweeps)),
+               "mb4_ensemble_set_sweeps")
+
+    def sweeps(self) -> int:
+        return load_library().mb4_ensemble_sweeps(self._e)
+
+    def tune_all(self, steps: int = 32) -> tuple[int, int, dict]:
+        """Autotuner over region and sweeps: (region, sweeps, {(region,
+        sweeps): ms per step}) for the pairs tried."""
+        region = c_int32()
+        sweeps = c_int32()
+        ms = (c_double * (4 * MB4_REGION_COUNT))()
+        _check(load_library().mb4_ensemble_tune_all(self._e, int(steps), byref(region),
+                                                    byref(sweeps), ms),
+               "mb4_ensemble_tune_all")
+        times = {(r, sw + 1): ms[sw * MB4_REGION_COUNT + r]
+                 for sw in range(4) for r in range(MB4_REGION_COUNT)
+                 if ms[sw * MB4_REGION_COUNT + r] >= 0}
+        return region.value, sweeps.value, times
 
     def close(self) -> None:
         if getattr(self, "_e", None) is not None:

@@ -291,8 +291,11 @@ def test_ensemble_calls_reject_null(lib):
     assert lib.mb4_ensemble_member_stats(None, 0, None, None) == M.MB4_EINVAL
     assert lib.mb4_ensemble_set_region(None, 0) == M.MB4_EINVAL
     assert lib.mb4_ensemble_tune(None, 1, None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_tune_all(None, 1, None, None, None) == M.MB4_EINVAL
+    assert lib.mb4_ensemble_set_sweeps(None, 3) == M.MB4_EINVAL
     assert lib.mb4_ensemble_size(None) == -1
     assert lib.mb4_ensemble_region(None) == -1
+    assert lib.mb4_ensemble_sweeps(None) == -1
     lib.mb4_ensemble_destroy(None)
 
 

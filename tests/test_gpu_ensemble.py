@@ -133,6 +133,40 @@ def test_tune_keeps_the_trajectory():
             assert all(np.array_equal(x, y) for x, y in zip(a.get_state(i), b.get_state(i)))
 
 
+def test_tune_all_picks_a_shape_and_keeps_the_trajectory():
+    # After the joint region/sweeps tuner the states are those before it, and
+    # the run continues exactly as an ensemble set to the chosen pair.
+    torch_cuda()
+    inputs = _inputs(MEMBERS)
+    with _ensemble(MEMBERS, inputs) as a, _ensemble(MEMBERS, inputs) as b:
+        assert a.step(5) == M.MB4_OK and b.step(5) == M.MB4_OK
+        region, sweeps, ms = b.tune_all(3)
+        assert (region, sweeps) in ms and b.region() == region and b.sweeps() == sweeps
+        assert 2 <= sweeps <= 4 and all(sw >= 2 for _, sw in ms)
+        assert ms[(region, sweeps)] == min(ms.values())
+        for i in range(len(MEMBERS)):
+            assert b.member_stats(i)["steps_done"] == 5
+            assert all(np.array_equal(x, y) for x, y in zip(a.get_state(i), b.get_state(i)))
+        a.set_sweeps(sweeps)
+        a.set_region(region)
+        assert a.step(7) == M.MB4_OK and b.step(7) == M.MB4_OK
+        for i in range(len(MEMBERS)):
+            assert all(np.array_equal(x, y) for x, y in zip(a.get_state(i), b.get_state(i)))
+
+
+def test_set_sweeps_matches_an_ensemble_created_with_them():
+    torch_cuda()
+    inputs = _inputs(MEMBERS)
+    with _ensemble(MEMBERS, inputs) as a, _ensemble(MEMBERS, inputs, inner_sweeps=4) as b:
+        a.set_sweeps(4)
+        assert a.sweeps() == 4
+        with pytest.raises(M.Mb4Error):
+            a.set_sweeps(5)
+        assert a.step(9) == M.MB4_OK and b.step(9) == M.MB4_OK
+        for i in range(len(MEMBERS)):
+            assert all(np.array_equal(x, y) for x, y in zip(a.get_state(i), b.get_state(i)))
+
+
 def test_failing_member_keeps_its_state_and_others_advance():
     # Member 1's step is far too large for the simplified Newton iteration
     # (Sec. 2.2): the call reports MB4_ENOCONV, member 1 keeps its initial
