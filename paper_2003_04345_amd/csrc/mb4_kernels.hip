@@ -619,11 +619,24 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
     vv[j] = L.V[gsite[j]];
   }
   if (FIRST) {
-    for (int e = threadIdx.x; e < UN; e += kSolveThreads) {
-      const int ex = e % UX, ey = e / UX;
-      const int site =
-          wrap_in(ty0 - H - 1 + ey, ny, fast) * nx + wrap_in(tx0 - H - 1 + ex, nx, fast);
-      su[e] = (PREV && pmode != 0) ? u_prev(site) : L.u0[site];
+    // All loads of the staging first, then the stores, so that the rounds'
+    // latencies overlap.
+    constexpr int NS = (UN + kSolveThreads - 1) / kSolveThreads;
+    double2 st[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int e = threadIdx.x + k * kSolveThreads;
+      if (e < UN) {
+        const int ex = e % UX, ey = e / UX;
+        const int site =
+            wrap_in(ty0 - H - 1 + ey, ny, fast) * nx + wrap_in(tx0 - H - 1 + ex, nx, fast);
+        st[k] = (PREV && pmode != 0) ? u_prev(site) : L.u0[site];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int e = threadIdx.x + k * kSolveThreads;
+      if (e < UN) su[e] = st[k];
     }
     __syncthreads();
   }
