@@ -101,6 +101,17 @@ typedef struct {
  * root.  At most 4 inner sweeps; mb4_newton_update and mb4_stage_solve stay
  * FP64. */
 #define MB4_FLAG_FP32_SOLVE 4u
+/* mb4_options.flags: spectrally preconditioned stage solves, for kinetic
+ * operators too stiff for block-Jacobi sweeps (the continuum -Delta_h of
+ * Sec. 3: t_hop = 1/h_x^2, diag_shift = 4 t_hop, where h lambda_i t_hop
+ * reaches ~10).  Each stage system of Eq. MB4_5 is solved by inner_sweeps
+ * Richardson iterations preconditioned by its constant-coefficient part (the
+ * hopping, diag_shift and the mean potential), which the 2D discrete Fourier
+ * transform diagonalises; one iteration contracts the error by at most
+ * h |lambda_i| times the largest on-site deviation (V - mean V plus the
+ * nonlinear Jacobian).  Sides up to 1024, FP64 only (not with
+ * MB4_FLAG_FP32_SOLVE), up to 64 iterations; single states only. */
+#define MB4_FLAG_SPECTRAL_SOLVE 8u
 
 typedef struct mb4_state mb4_state;
 

@@ -16,8 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmb4.so")
-SOURCES = ["mb4_kernels.hip", "mb4_runtime.hip", "mb4_engine.hip", "mb4_ensemble.hip",
-           "mb4_server.hip"]
+SOURCES = ["mb4_kernels.hip", "mb4_spectral.hip", "mb4_runtime.hip", "mb4_engine.hip",
+           "mb4_ensemble.hip", "mb4_server.hip"]
 ARCH = "gfx950"
 
 

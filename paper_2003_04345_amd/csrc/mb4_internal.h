@@ -131,10 +131,15 @@ hipError_t launch_stage_sweep(const Lattice& lat, CPlanes3 phib, CPlanes3 rin, P
 // phib <- (T^-1 (x) I) Phi(Uout); ||(T (x) I) rbar||_inf goes to *rslot if not
 // NULL.  Uin and Uout must not alias (blocks read the halo of Uin while
 // others write Uout).  Uout is not written when !from_u0 && !has_rbar.
+// xform: the stage fields hold X = U - e (x) u_0 instead of U (from_u0 then
+// means X = 0), as on the fused path; the final update is u_0 + X_3 + (T
+// rbar)_3.  Rounding then stays at the size of X, not of U, which matters
+// for stiff kinetic operators.
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                                   bool has_rbar, bool from_u0, Planes3 phib,
                                   unsigned long long* rslot, ConvCheck check, ConvCheck fin,
-                                  double2* u0_out, hipStream_t stream, LaunchEvents ev = {});
+                                  double2* u0_out, hipStream_t stream, LaunchEvents ev = {},
+                                  bool xform = false);
 
 // ---------------------------------------------------------------------------
 // The fused path (at most four sweeps per stage solve) holds the Newton
@@ -203,6 +208,31 @@ hipError_t launch_iterate(const Lattice& lat, CPlanes3 Xin, Planes3 Xout, int sw
 hipError_t launch_final_update(const Lattice& lat, CPlanes3 X, ConvCheck check, ConvCheck fin,
                                StepOut so, hipStream_t stream, LaunchEvents ev = {},
                                const Multi& mu = {});
+
+// ---------------------------------------------------------------------------
+// Spectrally preconditioned stage solves (mb4_spectral.hip), for kinetic
+// operators too stiff for block-Jacobi sweeps.  One Richardson iteration of
+// the three stage systems is launch_spectral_residual (s = -Phibar - A r;
+// skipped on the first iteration, where r = 0 and s = -Phibar) and four
+// line-DFT passes (pass 0: rows of `in` times `sign` into io; pass 1:
+// columns and the preconditioner; pass 2: inverse rows; pass 3: inverse
+// columns, r += z (r = z if `first`), and ||(T (x) I) r||_inf to *rslot if
+// not NULL).  Every launch returns at once when `check` holds.  Sides up to
+// kMaxSpectralSide.
+constexpr int kMaxSpectralSide = 1024;
+
+struct SpectralArgs {
+  double kappa0;       // V_ref + shift: the preconditioner's on-site value
+  const double2* twx;  // e^{-2 pi i m / nx}, m = 0 .. nx-1 (device)
+  const double2* twy;  // e^{-2 pi i m / ny}, m = 0 .. ny-1 (device)
+};
+
+hipError_t launch_spectral_residual(const Lattice& lat, CPlanes3 phib, CPlanes3 r, Planes3 s,
+                                    ConvCheck check, hipStream_t stream, LaunchEvents ev = {});
+hipError_t launch_spectral_pass(int pass, const Lattice& lat, CPlanes3 in, double sign,
+                                Planes3 io, Planes3 r, const SpectralArgs& sa, bool first,
+                                unsigned long long* rslot, ConvCheck check, hipStream_t stream,
+                                LaunchEvents ev = {});
 
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

@@ -239,14 +239,20 @@ __global__ __launch_bounds__(256) void k_clear_u64(unsigned long long* p, int n)
 // ---------------------------------------------------------------------------
 // Updated stage values and their linear combinations W_i = E_i0 u_0 +
 // sum_j E_ij U_j (Eq. fKu2) at one site.
-template <bool FROM_U0, bool HAS_RBAR>
+// The iterate at one site after the update of this pass, and the linear
+// stage combinations W_i (Eq. fKu2).  XFORM: the stage fields hold X = U -
+// e (x) u_0 (Un receives X, and W_i = c_i u_0 + sum_j E_ij X_j, the full rows
+// of E summing to c_i), which keeps the rounding of stored U out of W;
+// otherwise they hold U.
+template <bool FROM_U0, bool HAS_RBAR, bool XFORM>
 __device__ __forceinline__ void site_update(const Lattice& L, const CPlanes3& Uin,
                                             const CPlanes3& rb, int site, double2& u0,
                                             double2 (&Un)[3], double2 (&W)[3],
                                             unsigned long long& rm) {
   u0 = L.u0[site];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) Un[j] = FROM_U0 ? u0 : Uin.s[j][site];
+  for (int j = 0; j < 3; ++j)
+    Un[j] = FROM_U0 ? (XFORM ? make_double2(0.0, 0.0) : u0) : Uin.s[j][site];
   rm = 0ull;
   if (HAS_RBAR) {
     double2 r[3];
@@ -262,17 +268,16 @@ __device__ __forceinline__ void site_update(const Lattice& L, const CPlanes3& Ui
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    W[i].x = MB4_E0[i] * u0.x + MB4_E[i][0] * Un[0].x + MB4_E[i][1] * Un[1].x +
-             MB4_E[i][2] * Un[2].x;
-    W[i].y = MB4_E0[i] * u0.y + MB4_E[i][0] * Un[0].y + MB4_E[i][1] * Un[1].y +
-             MB4_E[i][2] * Un[2].y;
+    const double e0 = XFORM ? MB4_C[i] : MB4_E0[i];
+    W[i].x = e0 * u0.x + MB4_E[i][0] * Un[0].x + MB4_E[i][1] * Un[1].x + MB4_E[i][2] * Un[2].x;
+    W[i].y = e0 * u0.y + MB4_E[i][0] * Un[0].y + MB4_E[i][1] * Un[1].y + MB4_E[i][2] * Un[2].y;
   }
 }
 
 // Final update or residual pass of Newton iteration `fin.prev` (see top).
 // `chk` skips the pass once an earlier iteration converged; `rslot` (may be
 // NULL) receives ||(T (x) I) rbar||_inf, used by the kernel-level entry point.
-template <bool FROM_U0, bool HAS_RBAR>
+template <bool FROM_U0, bool HAS_RBAR, bool XFORM>
 __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 Uin, Planes3 Uout,
                                                            CPlanes3 rb, Planes3 phib,
                                                            unsigned long long* rslot,
@@ -290,7 +295,11 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
       double2 r[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) r[m] = rb.s[m][site];
-      const double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
+      double2 base = FROM_U0 ? L.u0[site] : Uin.s[2][site];
+      if (XFORM && !FROM_U0) {
+        const double2 u = L.u0[site];
+        base = make_double2(u.x + base.x, u.y + base.y);
+      }
       const double2 d = t_apply(2, r);
       u0_out[site] = make_double2(base.x + d.x, base.y + d.y);
     }
@@ -305,7 +314,7 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
   const int site = gy * nx + gx;
   double2 u0, Un[3], W[3];
   unsigned long long rm;
-  site_update<FROM_U0, HAS_RBAR>(L, Uin, rb, site, u0, Un, W, rm);
+  site_update<FROM_U0, HAS_RBAR, XFORM>(L, Uin, rb, site, u0, Un, W, rm);
 #pragma unroll
   for (int i = 0; i < 3; ++i) sw[i][ly + 1][lx + 1] = W[i];
 
@@ -328,7 +337,7 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
     const int hs = wrap(c.y0 + hy - 1, ny) * nx + wrap(c.x0 + hx - 1, nx);
     double2 hu0, hUn[3], hW[3];
     unsigned long long hrm;
-    site_update<FROM_U0, HAS_RBAR>(L, Uin, rb, hs, hu0, hUn, hW, hrm);
+    site_update<FROM_U0, HAS_RBAR, XFORM>(L, Uin, rb, hs, hu0, hUn, hW, hrm);
 #pragma unroll
     for (int i = 0; i < 3; ++i) sw[i][hy][hx] = hW[i];
   }
@@ -349,13 +358,15 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
       const double awq = -t * sq + vs * W[i].y;
       phi[i] = make_double2(awq, -awp);
     }
-    // Cubic part (Eq. fIu2) by 6-node Gauss-Legendre, exact for degree 11.
+    // Cubic part (Eq. fIu2) by 6-node Gauss-Legendre, exact for degree 11
+    // (XFORM: the nodes are u_0 + sum_j L_qj X_j, the l_j summing to one).
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      const double zp = MB4_GL_L[q][0] * u0.x + MB4_GL_L[q][1] * Un[0].x +
-                        MB4_GL_L[q][2] * Un[1].x + MB4_GL_L[q][3] * Un[2].x;
-      const double zq = MB4_GL_L[q][0] * u0.y + MB4_GL_L[q][1] * Un[0].y +
-                        MB4_GL_L[q][2] * Un[1].y + MB4_GL_L[q][3] * Un[2].y;
+      const double l0 = XFORM ? 1.0 : MB4_GL_L[q][0];
+      const double zp = l0 * u0.x + MB4_GL_L[q][1] * Un[0].x + MB4_GL_L[q][2] * Un[1].x +
+                        MB4_GL_L[q][3] * Un[2].x;
+      const double zq = l0 * u0.y + MB4_GL_L[q][1] * Un[0].y + MB4_GL_L[q][2] * Un[1].y +
+                        MB4_GL_L[q][3] * Un[2].y;
       const double gn = g * (zp * zp + zq * zq);
       const double fp = gn * zq, fq = -gn * zp;
 #pragma unroll
@@ -367,8 +378,9 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
     // Phi_i = U_i - u_0 - h int A_{c_i,z} f(U_z) dz (Eq. Phidefinition).
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      phi[i].x = (Un[i].x - u0.x) - h * phi[i].x;
-      phi[i].y = (Un[i].y - u0.y) - h * phi[i].y;
+      const double2 x = XFORM ? Un[i] : make_double2(Un[i].x - u0.x, Un[i].y - u0.y);
+      phi[i].x = x.x - h * phi[i].x;
+      phi[i].y = x.y - h * phi[i].y;
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -1240,20 +1252,23 @@ hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream) {
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
                                   bool has_rbar, bool from_u0, Planes3 phib,
                                   unsigned long long* rslot, ConvCheck check, ConvCheck fin,
-                                  double2* u0_out, hipStream_t stream, LaunchEvents ev) {
+                                  double2* u0_out, hipStream_t stream, LaunchEvents ev,
+                                  bool xform) {
   const dim3 grid(tile_blocks(lat.nx, lat.ny)), block(kTile);
-  if (from_u0 && has_rbar)
-    MB4_LAUNCH((k_update_residual<true, true>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check, fin, u0_out);
-  else if (from_u0)
-    MB4_LAUNCH((k_update_residual<true, false>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check, fin, u0_out);
-  else if (has_rbar)
-    MB4_LAUNCH((k_update_residual<false, true>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check, fin, u0_out);
-  else
-    MB4_LAUNCH((k_update_residual<false, false>), grid, block, ev, lat, Uin, Uout, rbar, phib,
-               rslot, check, fin, u0_out);
+#define MB4_UPD(F, R, X)                                                                      \
+  MB4_LAUNCH((k_update_residual<F, R, X>), grid, block, ev, lat, Uin, Uout, rbar, phib, rslot, \
+             check, fin, u0_out)
+  if (xform) {
+    if (from_u0 && has_rbar) MB4_UPD(true, true, true);
+    if (from_u0) MB4_UPD(true, false, true);
+    if (has_rbar) MB4_UPD(false, true, true);
+    MB4_UPD(false, false, true);
+  }
+  if (from_u0 && has_rbar) MB4_UPD(true, true, false);
+  if (from_u0) MB4_UPD(true, false, false);
+  if (has_rbar) MB4_UPD(false, true, false);
+  MB4_UPD(false, false, false);
+#undef MB4_UPD
 }
 
 const char* region_name(int region) {

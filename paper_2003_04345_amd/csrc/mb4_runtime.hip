@@ -97,6 +97,10 @@ struct mb4_state {
   double eps = kDefaultEps;
   bool relative_eps = false;  // eps scaled by ||u_0||_inf
   bool fp32 = false;          // FP32 inner stage solves
+  bool spectral = false;      // spectrally preconditioned stage solves
+  double kappa0 = 0.0;        // their preconditioner's on-site value
+  double2* twx = nullptr;     // their twiddles, nx and ny entries
+  double2* twy = nullptr;
   int max_newton = kDefaultMaxNewton;
   int sweeps = kDefaultSweeps;
   hipStream_t stream = nullptr;
@@ -308,8 +312,12 @@ int launch_events(mb4_state* s, int cls, int step, int iter, mb4::LaunchEvents* 
 // built in place), then any further sweeps one pass each, alternating between
 // rb and ra.  The pass that produces the solution records ||r^iter||_inf in
 // rec[iter].  `*result` receives the planes that hold the solution.
+int enqueue_spectral_solve(mb4_state* s, const Lattice& L, int step, int iter,
+                           unsigned long long* rec, double2* const** result);
+
 int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned long long* rec,
                   double2* const** result) {
+  if (s->spectral) return enqueue_spectral_solve(s, L, step, iter, rec, result);
   const ConvCheck chk = iter >= 2 ? conv_check(s, rec, iter - 1) : ConvCheck{nullptr, 0, 0.0, false};
   const int fused = std::min(s->sweeps, mb4::kMaxFusedSweeps);
   const bool extra = s->sweeps > fused;
@@ -334,6 +342,37 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
     cur = out;
   }
   *result = cur;
+  return MB4_OK;
+}
+
+// Spectrally preconditioned stage solve of Newton iteration `iter` (see
+// mb4_spectral.hip): s->sweeps Richardson iterations into ra, rb as the
+// residual buffer.  In iteration 1 the residual at U^0 = e_3 (x) u_0 comes
+// first, from the one-sweep first solve (which stores it in phib and records
+// ||u_0||_inf; its own solution goes to rb and is not used).  The last
+// Richardson iteration records ||r^iter||_inf in rec[iter].
+int enqueue_spectral_solve(mb4_state* s, const Lattice& L, int step, int iter,
+                           unsigned long long* rec, double2* const** result) {
+  const ConvCheck none{nullptr, 0, 0.0, false};
+  const ConvCheck chk = iter >= 2 ? conv_check(s, rec, iter - 1) : none;
+  if (iter == 1)
+    LAUNCH(s, kFirstSolve, step, 1,
+           mb4::launch_first_solve(L, P(s->rb), 1, nullptr, rec, P(s->phib), s->q, ev_));
+  const mb4::SpectralArgs sa{s->kappa0, s->twx, s->twy};
+  for (int k = 0; k < s->sweeps; ++k) {
+    const bool last = k == s->sweeps - 1;
+    if (k > 0)
+      LAUNCH(s, kSweep, step, iter,
+             mb4::launch_spectral_residual(L, C(s->phib), C(s->ra), P(s->rb), chk, s->q, ev_));
+    const CPlanes3 in = k == 0 ? C(s->phib) : C(s->rb);
+    const double sign = k == 0 ? -1.0 : 1.0;
+    for (int pass = 0; pass < 4; ++pass)
+      LAUNCH(s, k == 0 ? kStageSolve : kSweep, step, iter,
+             mb4::launch_spectral_pass(pass, L, in, sign, P(s->rb), P(s->ra), sa, k == 0,
+                                       (pass == 3 && last) ? rec + iter : nullptr, chk, s->q,
+                                       ev_));
+  }
+  *result = s->ra;
   return MB4_OK;
 }
 
@@ -404,7 +443,7 @@ int enqueue_iterations_fused(mb4_state* s, int step, int count, unsigned long lo
 // Iterations first .. last of a single step (u_0 and u_1 in s->u0).
 int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long long* rec,
                        int first, int last) {
-  if (s->sweeps <= mb4::kMaxFusedSweeps)
+  if (s->sweeps <= mb4::kMaxFusedSweeps && !s->spectral)
     return enqueue_iterations_fused(s, 0, 1, rec, first, last);
   for (int l = first; l <= last; ++l) {
     double2* const* rfin = nullptr;
@@ -412,13 +451,14 @@ int enqueue_iterations(mb4_state* s, const Lattice& L, int step, unsigned long l
     if (rc != MB4_OK) return rc;
     const ConvCheck chk = (l >= 2) ? conv_check(s, rec, l - 1) : ConvCheck{nullptr, 0, 0.0, false};
     const ConvCheck fin = conv_check(s, rec, l);
-    // Iteration l writes U into Ua (l odd) or Ub (l even) and reads the other.
+    // Iteration l writes X = U - e (x) u_0 into Ua (l odd) or Ub (l even) and
+    // reads the other.
     double2* const(&uout)[3] = (l % 2 == 1) ? s->Ua : s->Ub;
     double2* const(&uin)[3] = (l % 2 == 1) ? s->Ub : s->Ua;
     const CPlanes3 rbar{{rfin[0], rfin[1], rfin[2]}};
     LAUNCH(s, kUpdateResidual, step, l,
            mb4::launch_update_residual(L, C(uin), P(uout), rbar, true, l == 1, P(s->phib),
-                                       nullptr, chk, fin, s->u0, s->q, ev_));
+                                       nullptr, chk, fin, s->u0, s->q, ev_, true));
   }
   return MB4_OK;
 }
@@ -477,7 +517,7 @@ void update_prediction(mb4_state* s, int batch_max) {
 int enqueue_batch(mb4_state* s, int count, int iters) {
   const Lattice L = lattice_of(s);
   HIP_TRY(mb4::launch_clear(s->ring, count * s->rec_len, s->q));
-  const bool fused = s->sweeps <= mb4::kMaxFusedSweeps;
+  const bool fused = s->sweeps <= mb4::kMaxFusedSweeps && !s->spectral;
   for (int k = 0; k < count; ++k) {
     unsigned long long* rec = s->ring + size_t(k) * s->rec_len;
     const int rc =
@@ -653,12 +693,20 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     if (opt->inner_sweeps > 0) o.inner_sweeps = opt->inner_sweeps;
     o.stream = opt->stream;
     o.mem_budget = opt->mem_budget;
-    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS | MB4_FLAG_FP32_SOLVE)) != 0)
+    if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS | MB4_FLAG_FP32_SOLVE |
+                        MB4_FLAG_SPECTRAL_SOLVE)) != 0)
       return fail(MB4_EINVAL, "unknown bits in flags");
     o.flags = opt->flags;
     if ((o.flags & MB4_FLAG_FP32_SOLVE) != 0 && o.inner_sweeps > mb4::kMaxFusedSweeps)
       return fail(MB4_EINVAL, "FP32 inner solves take at most %d sweeps",
                   mb4::kMaxFusedSweeps);
+    if ((o.flags & MB4_FLAG_SPECTRAL_SOLVE) != 0) {
+      if ((o.flags & MB4_FLAG_FP32_SOLVE) != 0)
+        return fail(MB4_EINVAL, "spectral stage solves are FP64 only");
+      if (lattice->nx > mb4::kMaxSpectralSide || lattice->ny > mb4::kMaxSpectralSide)
+        return fail(MB4_EINVAL, "spectral stage solves take sides up to %d",
+                    mb4::kMaxSpectralSide);
+    }
   }
   if (!all_finite(potential, size_t(sites)))
     return fail(MB4_EINVAL, "potential has non-finite entries");
@@ -684,6 +732,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   s->use_graphs = (o.flags & MB4_FLAG_NO_GRAPHS) == 0;
   s->relative_eps = (o.flags & MB4_FLAG_RELATIVE_EPS) != 0;
   s->fp32 = (o.flags & MB4_FLAG_FP32_SOLVE) != 0;
+  s->spectral = (o.flags & MB4_FLAG_SPECTRAL_SOLVE) != 0;
 
   int rc = MB4_OK;
   hipError_t e = hipGetDevice(&s->device);
@@ -710,6 +759,29 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
     rc = dalloc(s, reinterpret_cast<void**>(&s->partials),
                 mb4::energy_partials_count(s->nx, s->ny) * sizeof(double));
   if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->eout), 8 * sizeof(double));
+  if (rc == MB4_OK && s->spectral) {
+    // The preconditioner's constant part: the mean potential plus the shift,
+    // and the DFT twiddles e^{-2 pi i m / n} (rounded once from long double).
+    std::vector<double> vs(potential, potential + s->sites);
+    std::sort(vs.begin(), vs.end(), [](double a, double b) { return fabs(a) < fabs(b); });
+    long double sum = 0.0L;
+    for (double v : vs) sum += v;
+    s->kappa0 = double(sum / (long double)s->sites) + s->shift;
+    rc = dalloc(s, reinterpret_cast<void**>(&s->twx), sizeof(double2) * size_t(s->nx));
+    if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->twy), sizeof(double2) * size_t(s->ny));
+    for (int axis = 0; axis < 2 && rc == MB4_OK; ++axis) {
+      const int n = axis == 0 ? s->nx : s->ny;
+      std::vector<double2> tw(static_cast<size_t>(n));
+      const long double pi = 3.141592653589793238462643383279502884L;
+      for (int m = 0; m < n; ++m) {
+        const long double ang = -2.0L * pi * (long double)m / (long double)n;
+        tw[size_t(m)] = make_double2(double(cosl(ang)), double(sinl(ang)));
+      }
+      e = hipMemcpy(axis == 0 ? s->twx : s->twy, tw.data(), sizeof(double2) * size_t(n),
+                    hipMemcpyHostToDevice);
+      if (e != hipSuccess) rc = fail(MB4_EDEVICE, "twiddle upload: %s", hipGetErrorString(e));
+    }
+  }
   if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_ring), ring_bytes);
   if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_dbg), 2 * sizeof(unsigned long long));
   if (rc == MB4_OK) rc = halloc(s, reinterpret_cast<void**>(&s->h_eout), 8 * sizeof(double));

@@ -168,6 +168,8 @@ int mb4_server_create(uint64_t arena_bytes, int32_t max_active, int32_t batch_st
     if (opt->inner_sweeps < 0 || opt->inner_sweeps > mb4::kMaxFusedSweeps)
       return fail(MB4_EINVAL, "inner_sweeps of a server must be in [0, %d]",
                   mb4::kMaxFusedSweeps);
+    if ((opt->flags & MB4_FLAG_SPECTRAL_SOLVE) != 0)
+      return fail(MB4_EINVAL, "spectral stage solves are for single states (mb4_create)");
     if ((opt->flags & ~(MB4_FLAG_NO_GRAPHS | MB4_FLAG_RELATIVE_EPS | MB4_FLAG_FP32_SOLVE)) != 0)
       return fail(MB4_EINVAL, "unknown bits in flags");
     if (opt->eps > 0.0) o.eps = opt->eps;

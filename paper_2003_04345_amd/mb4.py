@@ -39,6 +39,7 @@ class mb4_options(Structure):
 MB4_FLAG_NO_GRAPHS = 1
 MB4_FLAG_RELATIVE_EPS = 2
 MB4_FLAG_FP32_SOLVE = 4
+MB4_FLAG_SPECTRAL_SOLVE = 8
 
 MB4_REGION_32x32 = 0
 MB4_REGION_64x16 = 1
@@ -302,7 +303,8 @@ class MB4State:
     def __init__(self, nx: int, ny: int, potential, g: float, h: float, t_hop: float = 1.0,
                  diag_shift: float = 0.0, eps: float = 0.0, max_newton: int = 0,
                  inner_sweeps: int = 0, stream: int | None = None, mem_budget: int = 0,
-                 graphs: bool = True, relative_eps: bool = False, fp32_solve: bool = False):
+                 graphs: bool = True, relative_eps: bool = False, fp32_solve: bool = False,
+                 spectral_solve: bool = False):
         self.nx, self.ny = int(nx), int(ny)
         self.sites = self.nx * self.ny
         opt = mb4_options_default()
@@ -316,7 +318,8 @@ class MB4State:
         opt.mem_budget = mem_budget
         opt.flags = ((0 if graphs else MB4_FLAG_NO_GRAPHS) |
                      (MB4_FLAG_RELATIVE_EPS if relative_eps else 0) |
-                     (MB4_FLAG_FP32_SOLVE if fp32_solve else 0))
+                     (MB4_FLAG_FP32_SOLVE if fp32_solve else 0) |
+                     (MB4_FLAG_SPECTRAL_SOLVE if spectral_solve else 0))
         self._h = mb4_create(mb4_lattice(self.nx, self.ny, t_hop, diag_shift), potential,
                              mb4_nonlinearity(g), h, opt)
 

@@ -116,7 +116,7 @@ def test_create_rejects_invalid_arguments(lib, kwargs):
 @pytest.mark.parametrize("field,value", [("eps", -1.0), ("eps", float("nan")), ("eps", 1.0),
                                          ("max_newton", -1), ("max_newton", 1001),
                                          ("inner_sweeps", -2), ("inner_sweeps", 65),
-                                         ("flags", 8), ("flags", 0x80000000)])
+                                         ("flags", 16), ("flags", 0x80000000)])
 def test_create_rejects_invalid_options(lib, field, value):
     opt = M.mb4_options_default()
     setattr(opt, field, value)
@@ -305,6 +305,35 @@ def test_fp32_solves_take_at_most_four_sweeps(lib):
     opt.inner_sweeps = 5
     rc, out = _create(opt=opt)
     assert rc == M.MB4_EINVAL and out.value is None
+
+
+def test_spectral_solves_are_fp64_and_limited_in_size(lib):
+    opt = M.mb4_options_default()
+    opt.flags = M.MB4_FLAG_SPECTRAL_SOLVE | M.MB4_FLAG_FP32_SOLVE
+    rc, out = _create(opt=opt)
+    assert rc == M.MB4_EINVAL and out.value is None
+    assert "FP64" in M.error_detail()
+    opt.flags = M.MB4_FLAG_SPECTRAL_SOLVE
+    for lat in (M.mb4_lattice(1025, 4, 1.0, 0.0), M.mb4_lattice(4, 1025, 1.0, 0.0)):
+        rc, out = _create(lat=lat, opt=opt)
+        assert rc == M.MB4_EINVAL and out.value is None
+        assert "1024" in M.error_detail()
+
+
+def test_spectral_flag_is_for_single_states(lib):
+    opt = M.mb4_options_default()
+    opt.flags = M.MB4_FLAG_SPECTRAL_SOLVE
+    lats = (M.mb4_lattice * 1)(M.mb4_lattice(8, 8, 1.0, 0.0))
+    nls = (M.mb4_nonlinearity * 1)(M.mb4_nonlinearity(1.0))
+    v = np.zeros(64)
+    pots = (ctypes.POINTER(ctypes.c_double) * 1)(v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    hs = (ctypes.c_double * 1)(0.01)
+    out = ctypes.c_void_p(1234)
+    rc = lib.mb4_ensemble_create(1, lats, pots, nls, hs, ctypes.byref(opt), ctypes.byref(out))
+    assert rc == M.MB4_EINVAL and "single states" in M.error_detail()
+    srv = ctypes.c_void_p(1234)
+    rc = lib.mb4_server_create(1 << 26, 4, 4, ctypes.byref(opt), ctypes.byref(srv))
+    assert rc == M.MB4_EINVAL and "single states" in M.error_detail()
 
 
 def test_server_struct_layouts_match_binding():
