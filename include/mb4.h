@@ -110,7 +110,9 @@ typedef struct {
  * transform diagonalises; one iteration contracts the error by at most
  * h |lambda_i| times the largest on-site deviation (V - mean V plus the
  * nonlinear Jacobian).  Sides up to 1024, FP64 only (not with
- * MB4_FLAG_FP32_SOLVE), up to 64 iterations; single states only. */
+ * MB4_FLAG_FP32_SOLVE), up to 64 iterations; single states only.  The
+ * kernel-level mb4_newton_update and mb4_stage_solve keep their block-Jacobi
+ * form. */
 #define MB4_FLAG_SPECTRAL_SOLVE 8u
 
 typedef struct mb4_state mb4_state;
