@@ -212,12 +212,12 @@ hipError_t launch_final_update(const Lattice& lat, CPlanes3 X, ConvCheck check, 
 // ---------------------------------------------------------------------------
 // Spectrally preconditioned stage solves (mb4_spectral.hip), for kinetic
 // operators too stiff for block-Jacobi sweeps.  One Richardson iteration of
-// the three stage systems is launch_spectral_residual (s = -Phibar - A r;
-// skipped on the first iteration, where r = 0 and s = -Phibar) and four
-// line-DFT passes (pass 0: rows of `in` times `sign` into io; pass 1:
-// columns and the preconditioner; pass 2: inverse rows; pass 3: inverse
-// columns, r += z (r = z if `first`), and ||(T (x) I) r||_inf to *rslot if
-// not NULL).  Every launch returns at once when `check` holds.  Sides up to
+// the three stage systems is four line-DFT passes: pass 0 forms
+// z = -Phibar - D r on its rows (D = A - M, the site-local part of the stage
+// matrix A that the preconditioner M leaves out; r = 0 if `first`) and
+// transforms them into io; pass 1: columns and M^{-1}; pass 2: inverse rows;
+// pass 3: inverse columns into r, and ||(T (x) I) r||_inf to *rslot if not
+// NULL.  Every launch returns at once when `check` holds.  Sides up to
 // kMaxSpectralSide.
 constexpr int kMaxSpectralSide = 1024;
 
@@ -227,10 +227,8 @@ struct SpectralArgs {
   const double2* twy;  // e^{-2 pi i m / ny}, m = 0 .. ny-1 (device)
 };
 
-hipError_t launch_spectral_residual(const Lattice& lat, CPlanes3 phib, CPlanes3 r, Planes3 s,
-                                    ConvCheck check, hipStream_t stream, LaunchEvents ev = {});
-hipError_t launch_spectral_pass(int pass, const Lattice& lat, CPlanes3 in, double sign,
-                                Planes3 io, Planes3 r, const SpectralArgs& sa, bool first,
+hipError_t launch_spectral_pass(int pass, const Lattice& lat, CPlanes3 phib, Planes3 io,
+                                Planes3 r, const SpectralArgs& sa, bool first,
                                 unsigned long long* rslot, ConvCheck check, hipStream_t stream,
                                 LaunchEvents ev = {});
 

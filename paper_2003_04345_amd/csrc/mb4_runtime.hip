@@ -346,8 +346,8 @@ int enqueue_solve(mb4_state* s, const Lattice& L, int step, int iter, unsigned l
 }
 
 // Spectrally preconditioned stage solve of Newton iteration `iter` (see
-// mb4_spectral.hip): s->sweeps Richardson iterations into ra, rb as the
-// residual buffer.  In iteration 1 the residual at U^0 = e_3 (x) u_0 comes
+// mb4_spectral.hip): s->sweeps Richardson iterations into ra, with rb as the
+// transform buffer.  In iteration 1 the residual at U^0 = e_3 (x) u_0 comes
 // first, from the one-sweep first solve (which stores it in phib and records
 // ||u_0||_inf; its own solution goes to rb and is not used).  The last
 // Richardson iteration records ||r^iter||_inf in rec[iter].
@@ -361,14 +361,9 @@ int enqueue_spectral_solve(mb4_state* s, const Lattice& L, int step, int iter,
   const mb4::SpectralArgs sa{s->kappa0, s->twx, s->twy};
   for (int k = 0; k < s->sweeps; ++k) {
     const bool last = k == s->sweeps - 1;
-    if (k > 0)
-      LAUNCH(s, kSweep, step, iter,
-             mb4::launch_spectral_residual(L, C(s->phib), C(s->ra), P(s->rb), chk, s->q, ev_));
-    const CPlanes3 in = k == 0 ? C(s->phib) : C(s->rb);
-    const double sign = k == 0 ? -1.0 : 1.0;
     for (int pass = 0; pass < 4; ++pass)
       LAUNCH(s, k == 0 ? kStageSolve : kSweep, step, iter,
-             mb4::launch_spectral_pass(pass, L, in, sign, P(s->rb), P(s->ra), sa, k == 0,
+             mb4::launch_spectral_pass(pass, L, C(s->phib), P(s->rb), P(s->ra), sa, k == 0,
                                        (pass == 3 && last) ? rec + iter : nullptr, chk, s->q,
                                        ev_));
   }

@@ -319,7 +319,10 @@ int mb4_server_poll(mb4_server* s, int32_t* queued, int32_t* active) {
     ++s->batches;
     std::vector<char> is_failed(m, 0);
     for (int f : failed) is_failed[size_t(f)] = 1;
+    // Every finished request leaves the active list, even if copying one
+    // back fails: its range is free again, so it must not stay a member.
     std::vector<int64_t> still;
+    int first_err = MB4_OK;
     for (size_t i = 0; i < m; ++i) {
       Request& r = s->reqs[s->active[i]];
       r.done += before[i] - remaining[i];
@@ -327,12 +330,13 @@ int mb4_server_poll(mb4_server* s, int32_t* queued, int32_t* active) {
       s->site_steps += double(before[i] - remaining[i]) * r.desc.nx * r.desc.ny;
       if (is_failed[i] || r.done >= r.steps) {
         rc = retire(s, s->active[i], is_failed[i] != 0);
-        if (rc != MB4_OK) return rc;
+        if (rc != MB4_OK && first_err == MB4_OK) first_err = rc;
       } else {
         still.push_back(s->active[i]);
       }
     }
     s->active.swap(still);
+    if (first_err != MB4_OK) return first_err;
   }
   if (queued) *queued = int32_t(s->queue.size());
   if (active) *active = int32_t(s->active.size());

@@ -3,24 +3,28 @@
 // t = 1/h_x^2, diagonal shift 4 t) makes h lambda_i t reach ~10 per link,
 // where the sweeps of k_stage_solve diverge.
 //
-// The stage system of Eq. MB4_5, (I - h lambda_i J) rbar_i = -Phibar_i, is
-// solved by preconditioned Richardson iterations
-//   rbar <- rbar + M_i^{-1} (-Phibar_i - (I - h lambda_i J) rbar)
-// with M_i the constant-coefficient part of I - h lambda_i J.  Written for
-// psi = p + i q, S acts as multiplication by -i, so with K_c = V_ref + shift
-// - t * (sum over the four neighbours), M_i psi = (1 + i h lambda_i K_c) psi,
-// which the 2D discrete Fourier transform diagonalises: mode (kx, ky) is
-// multiplied by 1 + i h lambda_i kappa, kappa = V_ref + shift
-// - 2 t (cos(2 pi kx / nx) + cos(2 pi ky / ny)).  |1 + i b| >= 1, so one
-// iteration contracts the error by at most h lambda_i ||V - V_ref + N(u_0)||,
-// the site-local part that M leaves out.
+// The stage system of Eq. MB4_5, A_i rbar_i = -Phibar_i with
+// A_i = I - h lambda_i J, is solved by preconditioned Richardson iterations
+// with M_i the constant-coefficient part of A_i.  Written for psi = p + i q,
+// S acts as multiplication by -i, so with K_c = V_ref + shift - t * (sum
+// over the four neighbours), M_i psi = (1 + i h lambda_i K_c) psi, which the
+// 2D discrete Fourier transform diagonalises: mode (kx, ky) is multiplied by
+// 1 + i h lambda_i kappa, kappa = V_ref + shift - 2 t (cos(2 pi kx / nx)
+// + cos(2 pi ky / ny)).  The rest, D_i = A_i - M_i, is a 2x2 block per site
+// (the potential's deviation from V_ref and the cubic term's Jacobian), so
+// the iteration
+//   rbar <- rbar + M_i^{-1} (-Phibar_i - A_i rbar) = M_i^{-1} (-Phibar_i - D_i rbar)
+// needs no stencil: its right-hand side is formed site by site as the first
+// transform reads it.  |1 + i b| >= 1, so one iteration contracts the error
+// by at most h lambda_i ||D_i||.
 //
 // The transforms are line DFTs done directly (O(n) per output, n <= 1024):
 // one block per grid line, the line of all three stages and the twiddles in
-// LDS.  Rows are transformed, then columns with the mode multiplication
-// fused in; the inverse runs rows, then columns with the update of rbar (and
-// on the last iteration the norm ||(T (x) I) rbar||_inf) fused in.  Every
-// line is owned by one block, so the passes work in place.
+// LDS.  Rows are transformed (their right-hand side formed on the way in),
+// then columns with the mode multiplication fused in; the inverse runs rows,
+// then columns, which store the new rbar (and on the last iteration reduce
+// ||(T (x) I) rbar||_inf).  Every line is owned by one block, so the passes
+// work in place.
 #include <float.h>
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -32,7 +36,6 @@ namespace mb4 {
 namespace {
 
 constexpr int kLineThreads = 256;
-constexpr int kResidualThreads = 256;
 
 __device__ __forceinline__ unsigned long long abs_bits_s(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(fabs(v)));
@@ -49,49 +52,15 @@ __device__ __forceinline__ bool converged_s(const ConvCheck& c) {
   return r <= tol;
 }
 
-// s_i = -Phibar_i - (I - h lambda_i J) r_i at every site, all three stages.
-// (I - h lambda_i J) r = B r + (h lambda_i t sum r_q, -h lambda_i t sum r_p)
-// with B = I - h lambda_i J_site the 2x2 site block (Eqs. JL, JR).
-__global__ __launch_bounds__(kResidualThreads) void k_spec_residual(Lattice L, CPlanes3 phib,
-                                                                  CPlanes3 r, Planes3 s,
-                                                                  ConvCheck chk) {
-  if (converged_s(chk)) return;
-  const int nx = L.nx, ny = L.ny;
-  const int site = blockIdx.x * kResidualThreads + threadIdx.x;
-  if (site >= nx * ny) return;
-  const int x = site % nx, y = site / nx;
-  const int xl = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
-  const int yd = y == 0 ? ny - 1 : y - 1, yu = y == ny - 1 ? 0 : y + 1;
-  const int sl = y * nx + xl, sr = y * nx + xr, sd = yd * nx + x, su = yu * nx + x;
-  const double2 u = L.u0[site];
-  const double vs = L.V[site] + L.shift;
-  const double pp = u.x * u.x, qq = u.y * u.y;
-  const double a = 2.0 * L.g * u.x * u.y;
-  const double bb = vs + L.g * (pp + 3.0 * qq);
-  const double cc = vs + L.g * (3.0 * pp + qq);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double hl = L.h * MB4_LAMBDA[i], ht = hl * L.t;
-    const double2 ri = r.s[i][site];
-    const double2 r1 = r.s[i][sl], r2 = r.s[i][sr], r3 = r.s[i][sd], r4 = r.s[i][su];
-    const double sp = (r1.x + r2.x) + (r3.x + r4.x);
-    const double sq = (r1.y + r2.y) + (r3.y + r4.y);
-    const double2 ph = phib.s[i][site];
-    const double ax = (1.0 - hl * a) * ri.x - hl * bb * ri.y + ht * sq;
-    const double ay = hl * cc * ri.x + (1.0 + hl * a) * ri.y - ht * sp;
-    s.s[i][site] = make_double2(-ph.x - ax, -ph.y - ay);
-  }
-}
-
 // One pass of line DFTs (see the file comment).  PASS 0: forward along x
-// (rows), input `in` times `sign` into io; PASS 1: forward along y
-// (columns) and multiplication by 1 / (1 + i h lambda_i kappa); PASS 2:
-// inverse along x; PASS 3: inverse along y, scaled by 1 / (nx ny), added to
-// r (or stored, on the first iteration), and the norm to *rslot if not NULL.
+// (rows) of -Phibar - D r (of -Phibar if `first`) into io; PASS 1: forward
+// along y (columns) and multiplication by 1 / (1 + i h lambda_i kappa);
+// PASS 2: inverse along x; PASS 3: inverse along y, scaled by 1 / (nx ny),
+// into r, and the norm to *rslot if not NULL.
 template <int PASS>
-__global__ __launch_bounds__(kLineThreads) void k_spec_lines(Lattice L, CPlanes3 in, double sign,
-                                                             Planes3 io, Planes3 r,
-                                                             SpectralArgs sa, int first,
+__global__ __launch_bounds__(kLineThreads) void k_spec_lines(Lattice L, CPlanes3 phib, Planes3 io,
+                                                             Planes3 r, SpectralArgs sa,
+                                                             int first,
                                                              unsigned long long* rslot,
                                                              ConvCheck chk) {
   if (converged_s(chk)) return;
@@ -107,14 +76,33 @@ __global__ __launch_bounds__(kLineThreads) void k_spec_lines(Lattice L, CPlanes3
   for (int e = threadIdx.x; e < n; e += kLineThreads) {
     const int site = site_of(e);
     stw[e] = tw[e];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double2 v = (PASS == 0) ? in.s[i][site] : io.s[i][site];
-      if (PASS == 0) {
-        v.x *= sign;
-        v.y *= sign;
+    if (PASS == 0) {
+      // D r with D = [[-hl a, -hl (b - kappa0)], [hl (c - kappa0), hl a]]:
+      // the site block of Eqs. JL, JR less M's on-site part kappa0.
+      double a = 0.0, db = 0.0, dc = 0.0;
+      if (!first) {
+        const double2 u = L.u0[site];
+        const double pp = u.x * u.x, qq = u.y * u.y;
+        const double dv = (L.V[site] + L.shift) - sa.kappa0;
+        a = 2.0 * L.g * u.x * u.y;
+        db = dv + L.g * (pp + 3.0 * qq);
+        dc = dv + L.g * (3.0 * pp + qq);
       }
-      buf[i][e] = v;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 ph = phib.s[i][site];
+        double2 v = make_double2(-ph.x, -ph.y);
+        if (!first) {
+          const double hl = L.h * MB4_LAMBDA[i];
+          const double2 ri = r.s[i][site];
+          v.x -= -hl * (a * ri.x + db * ri.y);
+          v.y -= hl * (dc * ri.x + a * ri.y);
+        }
+        buf[i][e] = v;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) buf[i][e] = io.s[i][site];
     }
   }
   __syncthreads();
@@ -155,14 +143,8 @@ __global__ __launch_bounds__(kLineThreads) void k_spec_lines(Lattice L, CPlanes3
       double2 rv[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        double2 v = make_double2(acc[i].x * scale, acc[i].y * scale);
-        if (!first) {
-          const double2 o = r.s[i][site];
-          v.x += o.x;
-          v.y += o.y;
-        }
-        r.s[i][site] = v;
-        rv[i] = v;
+        rv[i] = make_double2(acc[i].x * scale, acc[i].y * scale);
+        r.s[i][site] = rv[i];
       }
       if (rslot != nullptr) {
 #pragma unroll
@@ -200,20 +182,8 @@ __global__ __launch_bounds__(kLineThreads) void k_spec_lines(Lattice L, CPlanes3
 
 }  // namespace
 
-hipError_t launch_spectral_residual(const Lattice& lat, CPlanes3 phib, CPlanes3 r, Planes3 s,
-                                    ConvCheck check, hipStream_t stream, LaunchEvents ev) {
-  const int n = lat.nx * lat.ny;
-  const dim3 grid((n + kResidualThreads - 1) / kResidualThreads), block(kResidualThreads);
-  if (ev.start == nullptr && ev.stop == nullptr)
-    hipLaunchKernelGGL(k_spec_residual, grid, block, 0, stream, lat, phib, r, s, check);
-  else
-    hipExtLaunchKernelGGL(k_spec_residual, grid, block, 0, stream, ev.start, ev.stop, 0u, lat,
-                          phib, r, s, check);
-  return hipGetLastError();
-}
-
-hipError_t launch_spectral_pass(int pass, const Lattice& lat, CPlanes3 in, double sign,
-                                Planes3 io, Planes3 r, const SpectralArgs& sa, bool first,
+hipError_t launch_spectral_pass(int pass, const Lattice& lat, CPlanes3 phib, Planes3 io,
+                                Planes3 r, const SpectralArgs& sa, bool first,
                                 unsigned long long* rslot, ConvCheck check, hipStream_t stream,
                                 LaunchEvents ev) {
   if (lat.nx > kMaxSpectralSide || lat.ny > kMaxSpectralSide) return hipErrorInvalidValue;
@@ -223,11 +193,11 @@ hipError_t launch_spectral_pass(int pass, const Lattice& lat, CPlanes3 in, doubl
 #define MB4_SPEC_PASS(P)                                                                      \
   do {                                                                                        \
     if (ev.start == nullptr && ev.stop == nullptr)                                            \
-      hipLaunchKernelGGL(k_spec_lines<P>, grid, block, 0, stream, lat, in, sign, io, r, sa,   \
-                         f, rslot, check);                                                    \
+      hipLaunchKernelGGL(k_spec_lines<P>, grid, block, 0, stream, lat, phib, io, r, sa, f,    \
+                         rslot, check);                                                       \
     else                                                                                      \
       hipExtLaunchKernelGGL(k_spec_lines<P>, grid, block, 0, stream, ev.start, ev.stop, 0u,  \
-                            lat, in, sign, io, r, sa, f, rslot, check);                       \
+                            lat, phib, io, r, sa, f, rslot, check);                          \
   } while (0)
   switch (pass) {
     case 0: MB4_SPEC_PASS(0); break;
