@@ -359,13 +359,17 @@ int enqueue_spectral_solve(mb4_state* s, const Lattice& L, int step, int iter,
     LAUNCH(s, kFirstSolve, step, 1,
            mb4::launch_first_solve(L, P(s->rb), 1, nullptr, rec, P(s->phib), s->q, ev_));
   const mb4::SpectralArgs sa{s->kappa0, s->twx, s->twy};
+  LAUNCH(s, kStageSolve, step, iter,
+         mb4::launch_spectral_pass(0, L, C(s->phib), P(s->rb), P(s->ra), sa, nullptr, chk, s->q,
+                                   ev_));
   for (int k = 0; k < s->sweeps; ++k) {
     const bool last = k == s->sweeps - 1;
-    for (int pass = 0; pass < 4; ++pass)
-      LAUNCH(s, k == 0 ? kStageSolve : kSweep, step, iter,
-             mb4::launch_spectral_pass(pass, L, C(s->phib), P(s->rb), P(s->ra), sa, k == 0,
-                                       (pass == 3 && last) ? rec + iter : nullptr, chk, s->q,
-                                       ev_));
+    LAUNCH(s, kSweep, step, iter,
+           mb4::launch_spectral_pass(1, L, C(s->phib), P(s->rb), P(s->ra), sa, nullptr, chk,
+                                     s->q, ev_));
+    LAUNCH(s, kSweep, step, iter,
+           mb4::launch_spectral_pass(last ? 3 : 2, L, C(s->phib), P(s->rb), P(s->ra), sa,
+                                     last ? rec + iter : nullptr, chk, s->q, ev_));
   }
   *result = s->ra;
   return MB4_OK;
