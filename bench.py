@@ -397,11 +397,15 @@ def main(argv=None) -> int:
     steps = args.steps if args.steps is not None else cfg.steps
     v, p, q = L.make_inputs(cfg)
     # The paper's continuum runs take the spectrally preconditioned stage
-    # solves (block-Jacobi sweeps diverge on -Delta_h); more Richardson
-    # iterations where a delta-like potential is left to the iteration, and
-    # a tolerance relative to ||u_0||_inf where |u| = 5.
+    # solves (block-Jacobi sweeps diverge on -Delta_h), and a tolerance
+    # relative to ||u_0||_inf where |u| = 5.  The Richardson count is the
+    # fastest measured: the simplified Newton iteration itself contracts by
+    # only about 1e-2 per iteration there, so more exact stage solves buy
+    # few Newton iterations (continuum70: 9 Newton iterations with 2
+    # Richardson iterations, 7 with 3 to 6, 0.39 vs 0.42+ ms/step; delta100:
+    # 3 with 4 to 12, 0.47 vs 0.53+ ms/step).
     continuum = cfg.initial == "cosine"
-    sweeps = args.sweeps or ((12 if cfg.origin_v is not None else 6) if continuum else 0)
+    sweeps = args.sweeps or ((4 if cfg.origin_v is not None else 2) if continuum else 0)
     st = M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, t_hop=cfg.t_hop, diag_shift=cfg.diag_shift,
                     eps=args.eps, inner_sweeps=sweeps, fp32_solve=args.fp32_solve,
                     spectral_solve=continuum,

@@ -25,22 +25,23 @@ def _state(cfg, v, sweeps, eps=EPS_PARITY, spectral=True, **kw):
                       spectral_solve=spectral, **kw)
 
 
-@pytest.mark.parametrize("n,steps", [(32, 10), (70, 5), (33, 4)])
-def test_continuum_steps_match_oracle(n, steps):
+@pytest.mark.parametrize("n,steps,sweeps", [(32, 10, 6), (70, 5, 6), (33, 4, 6), (70, 5, 2)])
+def test_continuum_steps_match_oracle(n, steps, sweeps):
     # u_0 reaches 5 here, so both sides stop at 1e-13 * ||u_0||_inf: with U
     # stored, the oracle's own residual has a rounding floor of about 2e-13
     # on the 70 x 70 continuum (h lambda ||K|| ~ 15).
     torch_cuda()
     cfg = _continuum("continuum70", n)
     v, p, q = L.make_inputs(cfg)
-    with _state(cfg, v, 6, eps=1e-13, relative_eps=True) as st:
+    with _state(cfg, v, sweeps, eps=1e-13, relative_eps=True) as st:
         st.set_state(p, q)
         assert st.step(steps) == M.MB4_OK, M.error_detail()
         gpu = st.psi()
         iters = st.last_stats()["newton_iters"]
     ref, _ = O.oracle_for(cfg, v, eps=1e-13, relative=True).run(p + 1j * q, steps)
     err = np.max(np.abs(gpu - ref))
-    print(f"continuum {n}x{n}, {steps} steps: max-abs vs oracle {err:.3e}, {iters} Newton iterations")
+    print(f"continuum {n}x{n}, {steps} steps, {sweeps} Richardson iterations: max-abs vs oracle "
+          f"{err:.3e}, {iters} Newton iterations")
     assert err <= 1e-12
 
 
@@ -73,14 +74,16 @@ def test_continuum70_conserves_energy_and_probability():
     assert worst_p <= 1e-7
 
 
-def test_delta_potential_matches_oracle():
-    # The delta-function-like potential of Sec. 3 (V = -50 at the origin),
-    # on a smaller grid: the site the preconditioner leaves out needs more
-    # Richardson iterations, not a different root.
+@pytest.mark.parametrize("n,sweeps", [(40, 12), (100, 4)])
+def test_delta_potential_matches_oracle(n, sweeps):
+    # The delta-function-like potential of Sec. 3 (V = -50 at the origin):
+    # the site the preconditioner leaves out needs more Richardson
+    # iterations, or more Newton iterations, not a different root.  100 x 100
+    # with 4 Richardson iterations is the full-size run as bench.py times it.
     torch_cuda()
-    cfg = _continuum("delta100", 40, origin_v=-50.0)
+    cfg = _continuum("delta100", n, origin_v=-50.0)
     v, p, q = L.make_inputs(cfg)
-    with _state(cfg, v, 12) as st:
+    with _state(cfg, v, sweeps) as st:
         st.set_state(p, q)
         h0 = st.energy()
         assert st.step(6) == M.MB4_OK, M.error_detail()
@@ -88,7 +91,7 @@ def test_delta_potential_matches_oracle():
         h1 = st.energy()
     ref, _ = O.oracle_for(cfg, v, eps=EPS_PARITY).run(p + 1j * q, 6)
     err = np.max(np.abs(gpu - ref))
-    print(f"delta potential 40x40, 6 steps: max-abs vs oracle {err:.3e}")
+    print(f"delta potential {n}x{n}, {sweeps} Richardson iterations, 6 steps: max-abs vs oracle {err:.3e}")
     assert err <= 1e-13
     assert abs(h1 - h0) <= 1e-14 * abs(h0)
 
