@@ -74,10 +74,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, sites: int):
+def measured_traffic(kernel: str, sites: int, region: str = "32x32", sweeps: int = 3):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
-    or None when there is none for the current kernel sources."""
+    or None when there is none for the current kernel sources and this launch
+    shape (region, sweeps)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -86,6 +87,8 @@ def measured_traffic(kernel: str, sites: int):
         return None
     entry = data.get("kernels", {}).get(kernel)
     if not entry or data.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    if (data.get("region"), data.get("inner_sweeps")) != (region, sweeps):
         return None
     return entry["bytes_per_site"] * sites
 
@@ -359,7 +362,8 @@ def main(argv=None) -> int:
     ap.add_argument("--members", type=int, default=L.ENSEMBLE_SIZE,
                     help="ensemble128: number of realisations")
     ap.add_argument("--tune-steps", type=int, default=32,
-                    help="ensemble128: steps the autotuner times per region/sweeps pair (0: no tuning)")
+                    help="steps the autotuner times per region/sweeps pair (0: no tuning; "
+                         "not for the continuum workloads)")
     ap.add_argument("--eps", type=float, default=0.0, help="Newton tolerance (0: library default)")
     ap.add_argument("--sweeps", type=int, default=0, help="block-Jacobi sweeps (0: default)")
     ap.add_argument("--fp32-solve", action="store_true",
@@ -412,6 +416,14 @@ def main(argv=None) -> int:
                     relative_eps=continuum and cfg.origin_v is None)
     st.set_state(p, q)
     h_start = st.energy()
+    # The region shape and block-Jacobi sweeps are the fastest pair that
+    # mb4_tune measures on this lattice (it restores the state afterwards).
+    tuning = None
+    if not continuum and args.tune_steps > 0 and not args.sweeps:
+        region, tuned_sweeps, ms = st.tune(min(args.tune_steps, 64))
+        tuning = {"region": M.REGION_NAMES[region], "inner_sweeps": tuned_sweeps,
+                  "ms_per_step": {f"{M.REGION_NAMES[r]}/{sw}": t
+                                  for (r, sw), t in sorted(ms.items())}}
     observables = []
 
     def observe(step_index):
@@ -451,6 +463,7 @@ def main(argv=None) -> int:
     h_end = st.energy()
     drift = abs(h_end - h_start) / abs(h_start)
     stats = st.last_stats()
+    region_used, sweeps_used = st.region(), st.sweeps()
     # Per-kernel timing: the same workload continued for up to 200 steps with
     # every launch timed by HIP events in its dispatch packet (launched one by
     # one, since the events belong to individual launches).
@@ -486,12 +499,15 @@ def main(argv=None) -> int:
                    "defect_v": cfg.defect_v, "sigma": cfg.sigma, "seed": cfg.seed,
                    "parallelism": "single GPU",
                    "newton_eps": args.eps or 1e-13, "newton_test": "absolute (Algorithm 1)",
-                   "inner_sweeps": stats["inner_sweeps"] // max(stats["newton_iters"], 1)},
+                   "inner_sweeps": stats["inner_sweeps"] // max(stats["newton_iters"], 1),
+                   "region": M.REGION_NAMES[region_used]},
         "energy_drift": drift,
         "energy_drift_ok": drift <= 1e-14,
         "newton_iters_last": stats["newton_iters"],
         "inner_sweeps_per_solve": stats["inner_sweeps"] // max(stats["newton_iters"], 1),
     }
+    if tuning is not None:
+        result["tuning"] = tuning
     if continuum:
         if not log_every:
             observe(steps)
@@ -506,7 +522,8 @@ def main(argv=None) -> int:
         per_launch_s = total_ms / 1e3 / max(n_launch, 1)
         bytes_launch = BYTES_PER_SITE[dominant] * sites
         achieved = bytes_launch / per_launch_s / 1e9
-        traffic = None if args.fp32_solve else measured_traffic(dominant, sites)
+        traffic = None if args.fp32_solve else measured_traffic(
+            dominant, sites, M.REGION_NAMES[region_used], sweeps_used)
         result["roofline"] = {
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

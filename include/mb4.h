@@ -222,6 +222,48 @@ MB4_API int mb4_stage_solve(mb4_state* state, const double* d_phibar, double* d_
                     int32_t sweeps);
 
 /* ------------------------------------------------------------------------
+ * Launch shape of the fused block-Jacobi path (inner_sweeps <= 4).
+ *
+ * Shapes of the solve regions (positions per block; the output tile is the
+ * region less the halo the sweeps need).  All give identical results; the
+ * speed depends on the lattice size, which mb4_tune and mb4_ensemble_tune
+ * measure. */
+#define MB4_REGION_32x32 0
+#define MB4_REGION_64x16 1
+#define MB4_REGION_32x16 2
+#define MB4_REGION_COUNT 3
+
+/* Selects the solve-region shape of a state (MB4_REGION_*; MB4_REGION_32x32
+ * at creation); with MB4_FLAG_FP32_SOLVE only MB4_REGION_32x32 is built.
+ * mb4_region returns it (-1 for NULL).  Errors: MB4_EINVAL. */
+MB4_API int mb4_set_region(mb4_state* state, int32_t region);
+MB4_API int32_t mb4_region(const mb4_state* state);
+
+/* Inner iterations per stage solve (Eq. MB4_5) of a state, as inner_sweeps
+ * of mb4_options: block-Jacobi sweeps (1 .. 64; at most 4 with
+ * MB4_FLAG_FP32_SOLVE), or Richardson iterations with
+ * MB4_FLAG_SPECTRAL_SOLVE.  The stage solves are inexact inner solves of the
+ * simplified Newton iteration, so the count changes the number of Newton
+ * iterations, not the root.  mb4_sweeps returns it (-1 for NULL).
+ * Errors: MB4_EINVAL. */
+MB4_API int mb4_set_sweeps(mb4_state* state, int32_t sweeps);
+MB4_API int32_t mb4_sweeps(const mb4_state* state);
+
+/* Autotuner of a state: times `steps` (1 .. 1024) steps under every region
+ * shape and 2 .. 4 sweeps (one untimed pass first), keeps the fastest pair,
+ * and restores the state, the step count and the statistics, so the run
+ * continues as if it had not been called.  A pair under which a step does
+ * not converge is skipped.  ms_per_step (may be NULL) receives
+ * 4 * MB4_REGION_COUNT times in ms per step, index
+ * (sweeps - 1) * MB4_REGION_COUNT + region, negative for a pair not timed;
+ * *best_region and *best_sweeps (either may be NULL) the pair kept.  Uses
+ * 16 bytes per site of temporary device memory.  Not with
+ * MB4_FLAG_SPECTRAL_SOLVE.  Errors: MB4_EINVAL, MB4_ENOMEM, MB4_EDEVICE (the
+ * state is restored and keeps its shape). */
+MB4_API int mb4_tune(mb4_state* state, int32_t steps, int32_t* best_region,
+                     int32_t* best_sweeps, double* ms_per_step);
+
+/* ------------------------------------------------------------------------
  * Ensembles: many independent lattice problems (disorder realisations, say)
  * advanced together.  Every Newton phase of every member runs in one launch
  * over all members' tiles, with the same kernels and arithmetic as a single
@@ -235,14 +277,6 @@ MB4_API int mb4_stage_solve(mb4_state* state, const double* d_phibar, double* d_
  * (potential, two u_0 buffers, two Newton-iterate fields of three stages)
  * plus the step records (8 * 32 * (max_newton + 1) bytes per member). */
 typedef struct mb4_ensemble mb4_ensemble;
-
-/* Shapes of the solve regions (positions per block; the output tile is the
- * region less the halo the sweeps need).  All give identical results; the
- * speed depends on the lattice sizes, which mb4_ensemble_tune measures. */
-#define MB4_REGION_32x32 0
-#define MB4_REGION_64x16 1
-#define MB4_REGION_32x16 2
-#define MB4_REGION_COUNT 3
 
 /* Creates an ensemble of `count` (1 .. 65536) members on the current device.
  *  lattices, nonlinearities, h: host arrays of `count` entries, each as for

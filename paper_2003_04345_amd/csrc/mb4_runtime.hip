@@ -27,6 +27,7 @@
 
 #include "mb4.h"
 #include "mb4_internal.h"
+#include "mb4_spectral.h"
 
 using mb4::CPlanes3;
 using mb4::ConvCheck;
@@ -103,6 +104,7 @@ struct mb4_state {
   double2* twy = nullptr;
   int max_newton = kDefaultMaxNewton;
   int sweeps = kDefaultSweeps;
+  int region = mb4::kRegion32x32;  // solve-region shape of the fused path
   hipStream_t stream = nullptr;
   // Stream the step kernels are enqueued to: `stream`, or cap_stream while a
   // batch is being captured into a graph.
@@ -417,11 +419,11 @@ int enqueue_iterations_fused(mb4_state* s, int step, int count, unsigned long lo
                                conv_check(s, prev_rec, last), src, s->u0};
         LAUNCH(s, kFinalFirst, step, 1,
                mb4::launch_first_solve_x(L, pp(xp(1)), s->sweeps, rec + 1, u0max, s->q, ev_,
-                                         mb4::Multi{}, mb4::kRegion32x32, s->fp32, &pv));
+                                         mb4::Multi{}, s->region, s->fp32, &pv));
       } else {
         LAUNCH(s, kFirstSolve, step, 1,
                mb4::launch_first_solve_x(L, pp(xp(1)), s->sweeps, rec + 1, u0max, s->q, ev_,
-                                         mb4::Multi{}, mb4::kRegion32x32, s->fp32, nullptr));
+                                         mb4::Multi{}, s->region, s->fp32, nullptr));
       }
       continue;
     }
@@ -430,7 +432,7 @@ int enqueue_iterations_fused(mb4_state* s, int step, int count, unsigned long lo
     LAUNCH(s, kIterate, step, j,
            mb4::launch_iterate(L, cp(xp(j)), pp(xp(l)), s->sweeps, rec + l, chk,
                                conv_check(s, rec, j), so, s->q, ev_, mb4::Multi{},
-                               mb4::kRegion32x32, s->fp32));
+                               s->region, s->fp32));
   }
   if (!emit_final) return MB4_OK;
   const ConvCheck chk = last >= 2 ? conv_check(s, rec, last - 1) : none;
@@ -918,6 +920,130 @@ int mb4_set_h(mb4_state* s, double h) {
   if (!isfinite(h) || h == 0.0) return fail(MB4_EINVAL, "h must be finite and non-zero");
   if (h != s->h) drop_graphs(s);
   s->h = h;
+  return MB4_OK;
+}
+
+int mb4_set_region(mb4_state* s, int32_t region) {
+  const int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (region < 0 || region >= MB4_REGION_COUNT)
+    return fail(MB4_EINVAL, "region must be in [0, %d)", MB4_REGION_COUNT);
+  if (s->fp32 && region != MB4_REGION_32x32)
+    return fail(MB4_EINVAL, "FP32 inner solves are built for MB4_REGION_32x32 only");
+  if (region != s->region) drop_graphs(s);
+  s->region = region;
+  return MB4_OK;
+}
+
+int32_t mb4_region(const mb4_state* s) { return s == nullptr ? -1 : s->region; }
+
+int mb4_set_sweeps(mb4_state* s, int32_t sweeps) {
+  const int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (sweeps < 1 || sweeps > kMaxSweeps)
+    return fail(MB4_EINVAL, "sweeps must be in [1, %d]", kMaxSweeps);
+  if (s->fp32 && sweeps > mb4::kMaxFusedSweeps)
+    return fail(MB4_EINVAL, "FP32 inner solves take at most %d sweeps", mb4::kMaxFusedSweeps);
+  if (sweeps != s->sweeps) drop_graphs(s);
+  s->sweeps = sweeps;
+  return MB4_OK;
+}
+
+int32_t mb4_sweeps(const mb4_state* s) { return s == nullptr ? -1 : s->sweeps; }
+
+int mb4_tune(mb4_state* s, int32_t steps, int32_t* best_region, int32_t* best_sweeps,
+             double* ms_per_step) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (steps < 1 || steps > 1024) return fail(MB4_EINVAL, "steps must be in [1, 1024]");
+  if (s->spectral)
+    return fail(MB4_EINVAL,
+                "mb4_tune covers block-Jacobi sweeps; set the Richardson count with "
+                "mb4_set_sweeps");
+  if ((rc = use_device(s)) != MB4_OK) return rc;
+  void* backup = nullptr;
+  hipError_t err = hipMalloc(&backup, s->sites * sizeof(double2));
+  if (err != hipSuccess) return fail(MB4_ENOMEM, "tune backup: %s", hipGetErrorString(err));
+  // Everything a trial changes: u_0 (device) and the step counters.
+  const int region0 = s->region, sweeps0 = s->sweeps;
+  const int64_t done0 = s->steps_done;
+  const int iters0 = s->last_iters, lsw0 = s->last_sweeps;
+  const double rn0 = s->last_rnorm;
+  const std::vector<double> res0 = s->last_res;
+  const int pred0 = s->predicted, lower0 = s->lower_batches;
+  auto restore = [&]() -> int {
+    s->steps_done = done0;
+    s->last_iters = iters0;
+    s->last_sweeps = lsw0;
+    s->last_rnorm = rn0;
+    s->last_res = res0;
+    HIP_TRY(hipMemcpyAsync(s->u0, backup, s->sites * sizeof(double2), hipMemcpyDeviceToDevice,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return MB4_OK;
+  };
+  if (ms_per_step != nullptr)
+    for (int k = 0; k < 4 * MB4_REGION_COUNT; ++k) ms_per_step[k] = -1.0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((err = hipMemcpyAsync(backup, s->u0, s->sites * sizeof(double2), hipMemcpyDeviceToDevice,
+                            s->stream)) != hipSuccess ||
+      (err = hipEventCreate(&t0)) != hipSuccess || (err = hipEventCreate(&t1)) != hipSuccess)
+    rc = fail(MB4_EDEVICE, "tune set-up: %s", hipGetErrorString(err));
+  int best_r = region0, best_s = sweeps0, pred_best = pred0;
+  double best_ms = -1.0;
+  for (int sw = 2; sw <= mb4::kMaxFusedSweeps && rc == MB4_OK; ++sw) {
+    for (int reg = 0; reg < MB4_REGION_COUNT && rc == MB4_OK; ++reg) {
+      if (mb4_set_region(s, reg) != MB4_OK || mb4_set_sweeps(s, sw) != MB4_OK) continue;
+      s->predicted = pred0;
+      s->lower_batches = lower0;
+      // One untimed pass (graph capture, caches, the iteration prediction),
+      // then the timed one.  A pair under which a step does not converge is
+      // skipped.
+      int trc = mb4_step(s, steps);
+      if (trc == MB4_OK) trc = restore();
+      if (trc == MB4_OK && (err = hipEventRecord(t0, s->stream)) != hipSuccess)
+        trc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+      if (trc == MB4_OK) trc = mb4_step(s, steps);
+      if (trc == MB4_OK && (err = hipEventRecord(t1, s->stream)) != hipSuccess)
+        trc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+      if (trc == MB4_OK && (err = hipEventSynchronize(t1)) != hipSuccess)
+        trc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+      float ms = 0.0f;
+      if (trc == MB4_OK && (err = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+        trc = fail(MB4_EDEVICE, "tune event: %s", hipGetErrorString(err));
+      const int pred = s->predicted;
+      if (trc != MB4_OK && trc != MB4_ENOCONV) {
+        rc = trc;
+        break;
+      }
+      if ((rc = restore()) != MB4_OK) break;
+      if (trc != MB4_OK) continue;
+      const double t = double(ms) / steps;
+      if (ms_per_step != nullptr) ms_per_step[(sw - 1) * MB4_REGION_COUNT + reg] = t;
+      if (best_ms < 0.0 || t < best_ms) {
+        best_ms = t;
+        best_r = reg;
+        best_s = sw;
+        pred_best = pred;
+      }
+    }
+  }
+  if (rc != MB4_OK) {
+    (void)restore();
+    best_r = region0;
+    best_s = sweeps0;
+    pred_best = pred0;
+  }
+  (void)mb4_set_region(s, best_r);
+  (void)mb4_set_sweeps(s, best_s);
+  s->predicted = pred_best;
+  s->lower_batches = 0;
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(backup);
+  if (rc != MB4_OK) return rc;
+  if (best_region) *best_region = best_r;
+  if (best_sweeps) *best_sweeps = best_s;
   return MB4_OK;
 }
 

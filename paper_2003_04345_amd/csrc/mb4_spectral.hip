@@ -31,6 +31,7 @@
 
 #include "mb4_constants.h"
 #include "mb4_internal.h"
+#include "mb4_spectral.h"
 
 namespace mb4 {
 namespace {

@@ -87,6 +87,12 @@ _SIGNATURES = {
     "mb4_energy": (c_int, [c_void_p, POINTER(c_double)]),
     "mb4_energy_components": (c_int, [c_void_p, POINTER(c_double)]),
     "mb4_set_h": (c_int, [c_void_p, c_double]),
+    "mb4_set_region": (c_int, [c_void_p, c_int32]),
+    "mb4_region": (c_int32, [c_void_p]),
+    "mb4_set_sweeps": (c_int, [c_void_p, c_int32]),
+    "mb4_sweeps": (c_int32, [c_void_p]),
+    "mb4_tune": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
+                         POINTER(c_double)]),
     "mb4_steps_done": (c_int64, [c_void_p]),
     "mb4_last_stats": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]),
     "mb4_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
@@ -247,6 +253,36 @@ def mb4_set_h(state, h: float) -> None:
     _check(load_library().mb4_set_h(state, float(h)), "mb4_set_h")
 
 
+def mb4_set_region(state, region: int) -> None:
+    _check(load_library().mb4_set_region(state, int(region)), "mb4_set_region")
+
+
+def mb4_region(state) -> int:
+    return int(load_library().mb4_region(state))
+
+
+def mb4_set_sweeps(state, sweeps: int) -> None:
+    _check(load_library().mb4_set_sweeps(state, int(sweeps)), "mb4_set_sweeps")
+
+
+def mb4_sweeps(state) -> int:
+    return int(load_library().mb4_sweeps(state))
+
+
+def mb4_tune(state, steps: int = 32) -> tuple[int, int, dict]:
+    """Autotuner of a single state over region and sweeps: (region, sweeps,
+    {(region, sweeps): ms per step}) for the pairs timed."""
+    region = c_int32()
+    sweeps = c_int32()
+    ms = (c_double * (4 * MB4_REGION_COUNT))()
+    _check(load_library().mb4_tune(state, int(steps), byref(region), byref(sweeps), ms),
+           "mb4_tune")
+    times = {(r, sw + 1): ms[sw * MB4_REGION_COUNT + r]
+             for sw in range(4) for r in range(MB4_REGION_COUNT)
+             if ms[sw * MB4_REGION_COUNT + r] >= 0}
+    return region.value, sweeps.value, times
+
+
 def mb4_steps_done(state) -> int:
     return int(load_library().mb4_steps_done(state))
 
@@ -351,6 +387,21 @@ class MB4State:
 
     def steps_done(self) -> int:
         return mb4_steps_done(self._h)
+
+    def set_region(self, region: int) -> None:
+        mb4_set_region(self._h, region)
+
+    def region(self) -> int:
+        return mb4_region(self._h)
+
+    def set_sweeps(self, sweeps: int) -> None:
+        mb4_set_sweeps(self._h, sweeps)
+
+    def sweeps(self) -> int:
+        return mb4_sweeps(self._h)
+
+    def tune(self, steps: int = 32) -> tuple[int, int, dict]:
+        return mb4_tune(self._h, steps)
 
     def last_stats(self) -> dict:
         return mb4_last_stats(self._h)

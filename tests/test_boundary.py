@@ -146,6 +146,11 @@ def test_null_arguments(lib):
     assert lib.mb4_last_stats(None, None, None, None) == M.MB4_EINVAL
     assert lib.mb4_newton_update(None, None, None, None, None) == M.MB4_EINVAL
     assert lib.mb4_stage_solve(None, None, None, 1) == M.MB4_EINVAL
+    assert lib.mb4_set_region(None, 0) == M.MB4_EINVAL
+    assert lib.mb4_region(None) == -1
+    assert lib.mb4_set_sweeps(None, 3) == M.MB4_EINVAL
+    assert lib.mb4_sweeps(None) == -1
+    assert lib.mb4_tune(None, 4, None, None, None) == M.MB4_EINVAL
     lib.mb4_destroy(None)
 
 
