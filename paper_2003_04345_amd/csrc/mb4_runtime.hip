@@ -971,6 +971,9 @@ int mb4_tune(mb4_state* s, int32_t steps, int32_t* best_region, int32_t* best_sw
   const double rn0 = s->last_rnorm;
   const std::vector<double> res0 = s->last_res;
   const int pred0 = s->predicted, lower0 = s->lower_batches;
+  // Trials are not part of the run: they stay out of the kernel profile.
+  const bool prof0 = s->prof_on;
+  s->prof_on = false;
   auto restore = [&]() -> int {
     s->steps_done = done0;
     s->last_iters = iters0;
@@ -1038,6 +1041,7 @@ int mb4_tune(mb4_state* s, int32_t steps, int32_t* best_region, int32_t* best_sw
   (void)mb4_set_sweeps(s, best_s);
   s->predicted = pred_best;
   s->lower_batches = 0;
+  s->prof_on = prof0;
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   (void)hipFree(backup);

@@ -55,7 +55,12 @@ def test_tune_restores_the_run_and_keeps_the_fastest_pair(fp32):
             assert s.step(7) == M.MB4_OK, M.error_detail()
         before = st.psi()
         stats0 = st.last_stats()
+        st.profile_enable(True)
+        prof0 = st.profile_read()
         region, sweeps, ms = st.tune(4)
+        # Trials stay out of the kernel profile.
+        assert st.profile_read() == prof0
+        st.profile_enable(False)
         print(f"fp32={fp32}: kept {M.REGION_NAMES[region]}/{sweeps}; "
               + ", ".join(f"{M.REGION_NAMES[r]}/{sw} {t:.4f}" for (r, sw), t in sorted(ms.items())))
         # Every pair was timed (FP32 solves: 32 x 32 only), the fastest kept.
