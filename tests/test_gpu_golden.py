@@ -25,13 +25,19 @@ def _golden(name):
     return g
 
 
-def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False, fp32_solve=False):
+def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False, fp32_solve=False,
+             tune=False):
+    """The workload as bench.py runs it: with tune, the launch shape is the
+    one mb4_tune keeps (region and sweeps), chosen after set_state."""
     cfg = L.CONFIGS[name]
     v, p, q = L.make_inputs(cfg)
     energies = []
     with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=eps, relative_eps=relative_eps,
                     fp32_solve=fp32_solve) as st:
         st.set_state(p, q)
+        if tune:
+            region, sweeps, _ = st.tune(16)
+            print(f"{name}: tuned to {M.REGION_NAMES[region]}/{sweeps}")
         energies.append((0, st.energy()))
         done = 0
         chunk = energy_every or steps
@@ -43,19 +49,21 @@ def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False, fp32_solve=Fa
         return st.psi(), energies
 
 
-@pytest.mark.parametrize("fp32_solve", [False, True])
+@pytest.mark.parametrize("fp32_solve,tune", [(False, False), (True, False), (False, True)])
 @pytest.mark.parametrize("name", ["lattice32", "lattice256", "lattice2048"])
-def test_workload_matches_stored_oracle_run(name, fp32_solve):
-    # Also with the FP32 inner solves, against the same FP64 oracle run.
+def test_workload_matches_stored_oracle_run(name, fp32_solve, tune):
+    # Also with the FP32 inner solves, and with the tuned launch shape that
+    # bench.py times, against the same FP64 oracle run.
     torch_cuda()
     g = _golden(name)
     every = g["energies"][1][0] if len(g["energies"]) > 1 else 0
     psi, energies = _gpu_run(name, g["steps"], g["eps"], energy_every=every,
-                             relative_eps=g["eps_relative"], fp32_solve=fp32_solve)
+                             relative_eps=g["eps_relative"], fp32_solve=fp32_solve, tune=tune)
     sites = np.array(g["sites"])
     err = np.max(np.abs(psi[sites] - (g["p"] + 1j * g["q"])))
     scale = np.max(np.abs(g["p"] + 1j * g["q"]))
-    print(f"{name}{' fp32 solves' if fp32_solve else ''}: {g['steps']} steps, "
+    print(f"{name}{' fp32 solves' if fp32_solve else ''}{' tuned' if tune else ''}: "
+          f"{g['steps']} steps, "
           f"max-abs {err:.3e} (max |psi| {scale:.3e})")
     # State parity bar of the workload definition: max-abs <= 1e-12 after the run.
     assert err <= 1e-12
@@ -66,18 +74,20 @@ def test_workload_matches_stored_oracle_run(name, fp32_solve):
             assert abs(e - ref[n]) <= 1e-14 * abs(ref[n])
 
 
-@pytest.mark.parametrize("fp32_solve", [False, True])
+@pytest.mark.parametrize("fp32_solve,tune", [(False, False), (True, False), (False, True)])
 @pytest.mark.parametrize("name,every", [("lattice32", 100), ("lattice256", 100),
                                         ("lattice2048", 500)])
-def test_full_run_conserves_energy(name, every, fp32_solve):
+def test_full_run_conserves_energy(name, every, fp32_solve, tune):
     # The paper reports the energy kept to 1e-14 .. 1e-16 (Sec. 3); the bar
     # here is a relative drift of at most 1e-14 over the whole run, at the
     # library's default Newton tolerance.
     torch_cuda()
     cfg = L.CONFIGS[name]
-    _, energies = _gpu_run(name, cfg.steps, 0.0, energy_every=every, fp32_solve=fp32_solve)
+    _, energies = _gpu_run(name, cfg.steps, 0.0, energy_every=every, fp32_solve=fp32_solve,
+                           tune=tune)
     h0 = energies[0][1]
     drift = max(abs(e - h0) for _, e in energies) / abs(h0)
-    print(f"{name}{' fp32 solves' if fp32_solve else ''}: {cfg.steps} steps, "
+    print(f"{name}{' fp32 solves' if fp32_solve else ''}{' tuned' if tune else ''}: "
+          f"{cfg.steps} steps, "
           f"energy drift {drift:.3e}")
     assert drift <= 1e-14
