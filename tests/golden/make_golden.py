@@ -31,7 +31,7 @@ import oracle as O  # noqa: E402
 CASES = {
     # name: (steps, eps, solver, energy_every, sampled)
     "lattice32": (1000, 1e-13, "direct", 100, False),
-    "lattice256": (20, 1e-13, "gmres", 10, True),
+    "lattice256": (1000, 1e-13, "gmres", 100, True),
     "lattice2048": (2, 1e-13, "gmres", 1, True),
 }
 
