@@ -535,6 +535,9 @@ def main(argv=None) -> int:
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "bytes_per_launch": bytes_launch, "mean_launch_us": per_launch_s * 1e6,
+            # The same launch time against the counter-measured HBM bytes.
+            "traffic_frac": (None if traffic is None
+                             else traffic / per_launch_s / 1e9 / HBM_PEAK_GBS),
         }
         result["kernel_time_ms"] = {k: {"launches": n, "total_ms": ms} for k, (n, ms) in prof.items()}
         result["kernel_timing_steps"] = prof_steps
