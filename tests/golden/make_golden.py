@@ -2,7 +2,8 @@
 
 Runs only the CPU oracle (oracle/) on the seeded workloads of lattice_inputs;
 nothing here touches the GPU library.  Usage:
-    python tests/golden/make_golden.py [lattice32] [lattice256] [lattice2048]
+    python tests/golden/make_golden.py [lattice32] [lattice256] [lattice2048] [continuum70]
+                                       [delta100]
 
 Each JSON file holds the workload name, the number of steps, the Newton
 tolerance (and whether it is relative to ||u_0||_inf), the oracle's stage solver, the site indices compared (all sites,
@@ -33,7 +34,14 @@ CASES = {
     "lattice32": (1000, 1e-13, "direct", 100, False),
     "lattice256": (1000, 1e-13, "gmres", 100, True),
     "lattice2048": (2, 1e-13, "gmres", 1, True),
+    # The continuum runs of Sec. 3: the whole t in [0, 0.5] of the 70 x 70
+    # comparison run, and the first 200 steps (t = 2) of the delta run.
+    "continuum70": (50, 1e-13, "direct", 5, True),
+    "delta100": (200, 1e-13, "direct", 25, True),
 }
+# Runs whose stopping test is relative to ||u_0||_inf (|u| reaches 5 there,
+# and the residual's rounding floor lies above the absolute 1e-13).
+RELATIVE = {"continuum70"}
 
 
 def sample_sites(cfg, n_packet=512, n_uniform=512, seed=2024):
@@ -57,13 +65,14 @@ def make(name: str) -> str:
     steps, eps, solver, every, sampled = CASES[name]
     cfg = L.CONFIGS[name]
     v, p, q = L.make_inputs(cfg)
-    orc = O.oracle_for(cfg, v, eps=eps, solver=solver)
+    relative = name in RELATIVE
+    orc = O.oracle_for(cfg, v, eps=eps, solver=solver, relative=relative)
     t0 = time.time()
     u, energies = orc.run(p + 1j * q, steps, energy_every=every)
     dt = time.time() - t0
     sites = sample_sites(cfg) if sampled else np.arange(cfg.sites)
     out = {
-        "workload": name, "steps": steps, "eps": eps, "eps_relative": False, "solver": solver,
+        "workload": name, "steps": steps, "eps": eps, "eps_relative": relative, "solver": solver,
         "generated_by": "tests/golden/make_golden.py (CPU oracle only)",
         "oracle_seconds": round(dt, 1),
         "sites": [int(s) for s in sites],

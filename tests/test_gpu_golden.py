@@ -1,6 +1,6 @@
-"""GPU runs of the three lattice workloads against stored oracle results
-(tests/golden/*_oracle.json, written by tests/golden/make_golden.py from the
-CPU oracle alone), and the energy invariant over the full runs."""
+"""GPU runs of the lattice and continuum workloads against stored oracle
+results (tests/golden/*_oracle.json, written by tests/golden/make_golden.py
+from the CPU oracle alone), and the energy invariant over the full runs."""
 import json
 import os
 
@@ -25,6 +25,11 @@ def _golden(name):
     return g
 
 
+# The continuum workloads run as bench.py runs them: spectrally
+# preconditioned stage solves with this many Richardson iterations.
+SPECTRAL_SWEEPS = {"continuum70": 2, "delta100": 4}
+
+
 def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False, fp32_solve=False,
              tune=False):
     """The workload as bench.py runs it: with tune, the launch shape is the
@@ -32,8 +37,10 @@ def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False, fp32_solve=Fa
     cfg = L.CONFIGS[name]
     v, p, q = L.make_inputs(cfg)
     energies = []
-    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, eps=eps, relative_eps=relative_eps,
-                    fp32_solve=fp32_solve) as st:
+    spectral = name in SPECTRAL_SWEEPS
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h, t_hop=cfg.t_hop, diag_shift=cfg.diag_shift,
+                    eps=eps, relative_eps=relative_eps, fp32_solve=fp32_solve,
+                    spectral_solve=spectral, inner_sweeps=SPECTRAL_SWEEPS.get(name, 0)) as st:
         st.set_state(p, q)
         if tune:
             region, sweeps, _ = st.tune(16)
@@ -72,6 +79,30 @@ def test_workload_matches_stored_oracle_run(name, fp32_solve, tune):
     for n, e in energies:
         if n in ref:
             assert abs(e - ref[n]) <= 1e-14 * abs(ref[n])
+
+
+@pytest.mark.parametrize("name", ["continuum70", "delta100"])
+def test_continuum_workload_matches_stored_oracle_run(name):
+    # The continuum runs of Sec. 3 against the oracle's direct stage solves:
+    # continuum70 over its whole t in [0, 0.5], delta100 over t in [0, 2].
+    torch_cuda()
+    g = _golden(name)
+    every = g["energies"][1][0]
+    psi, energies = _gpu_run(name, g["steps"], g["eps"], energy_every=every,
+                             relative_eps=g["eps_relative"])
+    sites = np.array(g["sites"])
+    ref_psi = g["p"] + 1j * g["q"]
+    err = np.max(np.abs(psi[sites] - ref_psi))
+    print(f"{name}: {g['steps']} steps, max-abs {err:.3e} (max |psi| {np.max(np.abs(ref_psi)):.3e})")
+    assert err <= 1e-12
+    # Energies along the run.  With the tolerance relative to ||u_0||_inf = 5
+    # (continuum70) each side's accepted root carries up to 5e-13 of Newton
+    # error, and H follows both to about 3e-14 (the drift floor of that run).
+    tol = 5e-14 if g["eps_relative"] else 1e-14
+    ref = dict(g["energies"])
+    worst = max(abs(e - ref[n]) / abs(ref[n]) for n, e in energies if n in ref)
+    print(f"{name}: energies vs oracle, worst relative difference {worst:.3e}")
+    assert worst <= tol
 
 
 @pytest.mark.parametrize("fp32_solve,tune", [(False, False), (True, False), (False, True)])
