@@ -22,8 +22,10 @@
  * simplified Newton iteration on the stage system (Eqs. Phidefinition,
  * Newton1) with the Jacobian frozen at u_0 (Eq. Jacobian2), decoupled by the
  * eigendecomposition of E into three stage solves (Eqs. MB4_4 - MB4_6) that
- * run concurrently in one kernel, until ||r||_inf <= eps * ||u_0||_inf, then
- * u_1 = U_{c_3} (c_3 = 1).  All arithmetic is IEEE double on the GPU.
+ * run concurrently in one kernel, until ||r^l||_inf <= eps (Algorithm 1; or
+ * eps * ||u_0||_inf with MB4_FLAG_RELATIVE_EPS), then u_1 = U_{c_3}
+ * (c_3 = 1).  All arithmetic is IEEE double on the GPU, except the inner
+ * stage solves under MB4_FLAG_FP32_SOLVE.
  *
  * Conventions for every entry point.
  *  - Return value: MB4_OK (0) or a negative MB4_E* code; mb4_strerror gives a
@@ -80,7 +82,8 @@ typedef struct {
                             (Algorithm 1; default 1e-13, the epsilon of Sec. 3),
                             or <= eps * ||u_0||_inf with MB4_FLAG_RELATIVE_EPS */
   int32_t max_newton;    /* Newton iterations before MB4_ENOCONV; default 50, <= 1000 */
-  int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve; default 3, <= 64 */
+  int32_t inner_sweeps;  /* block-Jacobi sweeps per stage solve (Richardson iterations
+                            with MB4_FLAG_SPECTRAL_SOLVE); default 3, <= 64 */
   void* stream;          /* hipStream_t for all work of the state; NULL = null stream */
   uint64_t mem_budget;   /* bytes of device memory the state may allocate; 0 = no limit */
   uint32_t flags;        /* MB4_FLAG_* bits; 0 = defaults */
