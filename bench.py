@@ -386,8 +386,9 @@ def main(argv=None) -> int:
         return copy_calibration(args.copy_calibration)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path "
+              "(lattices shard by 2D domain decomposition, ensembles and "
+              "requests by member; neither is implemented)", file=sys.stderr)
         return 2
 
     import torch
