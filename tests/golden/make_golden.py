@@ -33,7 +33,7 @@ CASES = {
     # name: (steps, eps, solver, energy_every, sampled)
     "lattice32": (1000, 1e-13, "direct", 100, False),
     "lattice256": (1000, 1e-13, "gmres", 100, True),
-    "lattice2048": (2, 1e-13, "gmres", 1, True),
+    "lattice2048": (20, 1e-13, "gmres", 5, True),
     # The continuum runs of Sec. 3: the whole t in [0, 0.5] of the 70 x 70
     # comparison run, and the first 200 steps (t = 2) of the delta run.
     "continuum70": (50, 1e-13, "direct", 5, True),
