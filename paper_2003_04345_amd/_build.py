@@ -31,7 +31,7 @@ def hipcc() -> str:
 def compile_command(out: str = LIB) -> list[str]:
     return [
         hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-        "-fvisibility=hidden", "-ffp-contract=fast",
+        "-fvisibility=hidden", "-ffp-contract=on",
         # no packed FP32 instructions anywhere in the device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",

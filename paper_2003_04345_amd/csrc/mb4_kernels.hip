@@ -544,8 +544,17 @@ __device__ __forceinline__ double2* step_dst(const StepOut& so, const Multi& mu,
   return (mu.todo != nullptr && mu.step == mu.todo[m] - 1) ? so.home : so.next;
 }
 
+// Threads of a solve block: two region positions per thread, except for the
+// 32 x 16 shape, which takes one.  Its blocks then run the shortest chain
+// (78-80 VGPRs, six waves per SIMD), which pays on lattices too small to
+// fill the chip with 32 x 32 blocks; on large lattices the tuner keeps the
+// 32 x 32 shape.  The shapes give the same bits: multiply-adds are fused
+// only within one source expression (-ffp-contract=on), whatever the
+// unrolling.
+constexpr int region_threads(int rx, int ry) { return rx == 32 && ry == 16 ? rx * ry : rx * ry / 2; }
+
 template <int RX, int RY, int H, int MODE, class RT>
-__global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(
+__global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(
     Lattice L, CPlanes3 phib_in, Planes3 phib_out, Planes3 out, unsigned long long* rslot,
     ConvCheck chk, FirstArgs fa, Multi mu, PrevStep pv) {
   constexpr bool FIRST = MODE != kSolvePlain;
@@ -553,7 +562,7 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
   constexpr bool PREV = MODE == kSolveFirstXPrev;
   static_assert(XOUT || sizeof(RT) == sizeof(double), "FP32 solves exist on the fused path only");
   using R2 = vec2_t<RT>;
-  constexpr int kSolveThreads = RX * RY / 2;
+  constexpr int kSolveThreads = region_threads(RX, RY);
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
   // PREV: how this step's u_0 is formed (PrevStep): 0 as it is, 1 the
   // previous step's u_0 + X_3, 2 the previous step's u_0 (it did not
@@ -793,18 +802,18 @@ __global__ __launch_bounds__(RX* RY / 2, sizeof(RT) == 4 ? 6 : 4) void k_stage_s
 // (the E_ij with j = 0..3 sum to c_i), the quadrature nodes are z_q = u_0 +
 // sum_j L_qj X_j (the l_j sum to one) and the residual is X_i - h (...).
 // A block works on an RX x RY region (32 x 32 with 512 threads by default),
-// two positions per thread: W_i (Eq. fKu2) on the whole region in LDS, the
+// region_threads() threads: W_i (Eq. fKu2) on the whole region in LDS, the
 // residual on the region less one ring, the sweeps on shrinking rings, and
 // the (RX - 2 - 2H) x (RY - 2 - 2H) tile in the middle is written back.  As
 // in k_stage_solve, each region position computes the values of its (wrapped)
 // lattice site from region neighbours only.
 template <int RX, int RY, int H, class RT>
-__global__ __launch_bounds__(RX* RY / 2, 4) void k_iterate(Lattice L, CPlanes3 Xin, Planes3 Xout,
+__global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L, CPlanes3 Xin, Planes3 Xout,
                                                           unsigned long long* rnext,
                                                           ConvCheck chk, ConvCheck fin,
                                                           StepOut so, Multi mu) {
   using R2 = vec2_t<RT>;
-  constexpr int kIterThreads = RX * RY / 2;
+  constexpr int kIterThreads = region_threads(RX, RY);
   const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
   if (w.skip) return;
   offset_check(chk, w.rec);
@@ -1305,7 +1314,7 @@ hipError_t launch_solve_region(const Lattice& lat, CPlanes3 phib_in, Planes3 phi
   const int h = sweeps - 1, tx = RX - 2 * h, ty = RY - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
                                      : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
-      block(RX * RY / 2);
+      block(region_threads(RX, RY));
   switch (sweeps) {
     case 1:
       MB4_LAUNCH((k_stage_solve<RX, RY, 0, MODE, RT>), grid, block, ev, lat, phib_in, phib_out,
@@ -1332,7 +1341,7 @@ hipError_t launch_iterate_region(const Lattice& lat, CPlanes3 Xin, Planes3 Xout,
   const int h = sweeps - 1, tx = RX - 2 - 2 * h, ty = RY - 2 - 2 * h;
   const dim3 grid(mu.desc != nullptr ? mu.blocks
                                      : ((lat.nx + tx - 1) / tx) * ((lat.ny + ty - 1) / ty)),
-      block(RX * RY / 2);
+      block(region_threads(RX, RY));
   switch (sweeps) {
     case 1:
       MB4_LAUNCH((k_iterate<RX, RY, 0, RT>), grid, block, ev, lat, Xin, Xout, rnext, check, fin,
