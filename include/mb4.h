@@ -129,9 +129,12 @@ MB4_API void mb4_options_default(mb4_options* opt);
  *  h: time step, finite and non-zero (negative steps run backwards).
  *  opt: NULL or options.
  *  out: receives the new state; set to NULL on failure.
- * The initial state psi is zero until mb4_set_state*.  Device memory: 264
- * bytes per site (potential, u_0, two stage-value fields, the transformed
- * residual and two stage-correction fields) plus a few kilobytes.
+ * The initial state psi is zero until mb4_set_state*.  Device memory: 136
+ * bytes per site (potential, two u_0 buffers, two fields of stage
+ * increments) plus a few kilobytes; 144 bytes per site more (the
+ * transformed residual and two stage-correction fields) once the state runs
+ * more than four inner sweeps or the spectral solves, or mb4_stage_solve
+ * with more than four sweeps, allocated on first use within mem_budget.
  * Errors: MB4_EINVAL, MB4_ENOMEM, MB4_EDEVICE. */
 MB4_API int mb4_create(const mb4_lattice* lattice, const double* potential,
                const mb4_nonlinearity* nonlinearity, double h,
@@ -247,8 +250,9 @@ MB4_API int32_t mb4_region(const mb4_state* state);
  * MB4_FLAG_FP32_SOLVE), or Richardson iterations with
  * MB4_FLAG_SPECTRAL_SOLVE.  The stage solves are inexact inner solves of the
  * simplified Newton iteration, so the count changes the number of Newton
- * iterations, not the root.  mb4_sweeps returns it (-1 for NULL).
- * Errors: MB4_EINVAL. */
+ * iterations, not the root.  More than four sweeps allocate the plain
+ * path's fields (see mb4_create) if the state has none yet.  mb4_sweeps
+ * returns it (-1 for NULL).  Errors: MB4_EINVAL, MB4_ENOMEM, MB4_EDEVICE. */
 MB4_API int mb4_set_sweeps(mb4_state* state, int32_t sweeps);
 MB4_API int32_t mb4_sweeps(const mb4_state* state);
 

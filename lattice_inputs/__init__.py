@@ -28,6 +28,8 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 STREAM_DISORDER = 0
 STREAM_DEFECTS = 1
+STREAM_AMPLITUDE = 2
+STREAM_PHASE = 3
 
 
 def _mix64(z: np.ndarray) -> np.ndarray:
@@ -81,9 +83,12 @@ class LatticeProblem:
     steps: int = 1000
     seed: int = 1
     energy_every: int = 0          # log energy every this many steps (0: ends only)
-    initial: str = "wavepacket"    # "wavepacket", or "cosine": 1 + 2 cos x + 2 cos y
+    initial: str = "wavepacket"    # "wavepacket", "cosine" (1 + 2 cos x + 2 cos y) or
+                                   # "random" (independent amplitude and phase per site)
     normalise: bool = True         # scale the initial state to sum |psi|^2 = 1
     origin_v: float | None = None  # potential at site 0 (the grid origin), if set
+    centre: tuple | None = None    # wavepacket centre (x, y); None: (nx // 2, ny // 2)
+    amp_range: tuple = (0.1, 0.5)  # "random": |psi_j| ~ Uniform[lo, hi]
     extra: dict = field(default_factory=dict)
 
     @property
@@ -119,12 +124,13 @@ def make_wavepacket(prob: LatticeProblem) -> tuple[np.ndarray, np.ndarray]:
     """Normalised Gaussian wavepacket, returned as (p, q) = (Re psi, Im psi).
 
     psi_j = exp(-d_j^2 / (2 sigma^2) + i k.r_j) with d_j the minimum-image
-    distance from site j to the centre (nx//2, ny//2) and r_j = (x, y) the
-    integer coordinates; then scaled so that sum |psi_j|^2 = 1.
+    distance from site j to the centre (nx//2, ny//2 unless prob.centre
+    names another site) and r_j = (x, y) the integer coordinates; then
+    scaled so that sum |psi_j|^2 = 1.
     """
     x = np.arange(prob.nx, dtype=np.float64)
     y = np.arange(prob.ny, dtype=np.float64)
-    cx, cy = prob.nx // 2, prob.ny // 2
+    cx, cy = (prob.nx // 2, prob.ny // 2) if prob.centre is None else prob.centre
     dx = np.abs(x - cx)
     dx = np.minimum(dx, prob.nx - dx)
     dy = np.abs(y - cy)
@@ -151,11 +157,23 @@ def make_cosine(prob: LatticeProblem) -> tuple[np.ndarray, np.ndarray]:
     return p, q
 
 
+def make_random_field(prob: LatticeProblem) -> tuple[np.ndarray, np.ndarray]:
+    """A delocalised state with signal on every site: |psi_j| uniform in
+    prob.amp_range (stream 2) and arg psi_j uniform in [0, 2 pi) (stream 3),
+    independently per site; not normalised."""
+    lo, hi = prob.amp_range
+    amp = lo + (hi - lo) * draw_uniform(prob.seed, STREAM_AMPLITUDE, prob.sites)
+    ph = 2.0 * math.pi * draw_uniform(prob.seed, STREAM_PHASE, prob.sites)
+    return amp * np.cos(ph), amp * np.sin(ph)
+
+
 def make_inputs(prob: LatticeProblem) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     """(V, p0, q0) for a problem; all float64 and C-contiguous."""
     v = make_potential(prob)
     if prob.initial == "cosine":
         p, q = make_cosine(prob)
+    elif prob.initial == "random":
+        p, q = make_random_field(prob)
     elif prob.initial == "wavepacket":
         p, q = make_wavepacket(prob)
     else:

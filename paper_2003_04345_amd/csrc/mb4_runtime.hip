@@ -103,6 +103,7 @@ struct mb4_state {
   double2* twx = nullptr;     // their twiddles, nx and ny entries
   double2* twy = nullptr;
   int max_newton = kDefaultMaxNewton;
+  uint64_t mem_budget = 0;  // 0: no limit
   int sweeps = kDefaultSweeps;
   int region = mb4::kRegion32x32;  // solve-region shape of the fused path
   hipStream_t stream = nullptr;
@@ -171,12 +172,18 @@ ConvCheck conv_check(const mb4_state* s, const unsigned long long* rec, int prev
   return ConvCheck{rec, prev, s->eps, s->relative_eps};
 }
 
-// Device bytes of a state: V (8 B/site), two u_0 buffers (2 x 16), two
-// stage-value fields (2 x 48), the transformed residual (48), two
-// stage-correction fields (2 x 48); plus the statistics records and the
-// energy partial sums.
-size_t footprint_bytes(size_t sites, int nx, int ny, int max_newton) {
-  return sites * 280 + size_t(kBatch + 1) * size_t(max_newton + 1) * 8 +
+// Device bytes of a state: V (8 B/site), two u_0 buffers (2 x 16) and two
+// stage-increment fields (2 x 48), plus the statistics records and the
+// energy partial sums.  The plain path (more than four sweeps, the spectral
+// solves, mb4_stage_solve beyond four sweeps) also needs the transformed
+// residual (48) and two stage-correction fields (2 x 48), allocated when
+// first needed.
+constexpr size_t kFusedBytesPerSite = 136;
+constexpr size_t kPlainBytesPerSite = 144;
+
+size_t footprint_bytes(size_t sites, int nx, int ny, int max_newton, bool plain) {
+  return sites * (kFusedBytesPerSite + (plain ? kPlainBytesPerSite : 0)) +
+         size_t(kBatch + 1) * size_t(max_newton + 1) * 8 +
          mb4::energy_partials_count(nx, ny) * sizeof(double) + 8 * sizeof(double);
 }
 
@@ -189,6 +196,35 @@ int dalloc(mb4_state* s, void** p, size_t bytes) {
   }
   s->device_allocs.push_back(*p);
   return MB4_OK;
+}
+
+// The plain path's fields (Phibar, and rbar ping-pong), allocated on first
+// use within the state's memory budget.
+int ensure_plain_fields(mb4_state* s) {
+  if (s->phib[0] != nullptr) return MB4_OK;
+  if (s->mem_budget != 0 &&
+      footprint_bytes(s->sites, s->nx, s->ny, s->max_newton, true) > s->mem_budget)
+    return fail(MB4_ENOMEM, "the plain path needs %zu bytes per site more, above mem_budget %llu",
+                kPlainBytesPerSite, static_cast<unsigned long long>(s->mem_budget));
+  const size_t field = s->sites * sizeof(double2);
+  int rc = MB4_OK;
+  for (int i = 0; i < 3 && rc == MB4_OK; ++i) {
+    rc = dalloc(s, reinterpret_cast<void**>(&s->phib[i]), field);
+    if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->ra[i]), field);
+    if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->rb[i]), field);
+  }
+  if (rc != MB4_OK) {
+    // Leave none of them half-made: the next call tries again.
+    for (int i = 0; i < 3; ++i)
+      for (double2** f : {&s->phib[i], &s->ra[i], &s->rb[i]}) {
+        if (*f == nullptr) continue;
+        (void)hipFree(*f);
+        s->device_allocs.erase(std::find(s->device_allocs.begin(), s->device_allocs.end(),
+                                         static_cast<void*>(*f)));
+        *f = nullptr;
+      }
+  }
+  return rc;
 }
 
 int halloc(mb4_state* s, void** p, size_t bytes) {
@@ -711,7 +747,9 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   }
   if (!all_finite(potential, size_t(sites)))
     return fail(MB4_EINVAL, "potential has non-finite entries");
-  const size_t need = footprint_bytes(size_t(sites), lattice->nx, lattice->ny, o.max_newton);
+  const bool plain = o.inner_sweeps > mb4::kMaxFusedSweeps || (o.flags & MB4_FLAG_SPECTRAL_SOLVE);
+  const size_t need =
+      footprint_bytes(size_t(sites), lattice->nx, lattice->ny, o.max_newton, plain);
   if (o.mem_budget != 0 && need > o.mem_budget)
     return fail(MB4_ENOMEM, "state needs %zu bytes, above mem_budget %llu", need,
                 static_cast<unsigned long long>(o.mem_budget));
@@ -727,6 +765,7 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   s->h = h;
   s->eps = o.eps;
   s->max_newton = o.max_newton;
+  s->mem_budget = o.mem_budget;
   s->sweeps = o.inner_sweeps;
   s->stream = static_cast<hipStream_t>(o.stream);
   s->q = s->stream;
@@ -748,10 +787,8 @@ int mb4_create(const mb4_lattice* lattice, const double* potential,
   for (int i = 0; i < 3; ++i) {
     alloc_field(&s->Ua[i]);
     alloc_field(&s->Ub[i]);
-    alloc_field(&s->phib[i]);
-    alloc_field(&s->ra[i]);
-    alloc_field(&s->rb[i]);
   }
+  if (rc == MB4_OK && plain) rc = ensure_plain_fields(s);
   s->rec_len = s->max_newton + 1;
   const size_t ring_bytes = size_t(kBatch) * s->rec_len * sizeof(unsigned long long);
   if (rc == MB4_OK) rc = dalloc(s, reinterpret_cast<void**>(&s->ring), ring_bytes);
@@ -944,6 +981,11 @@ int mb4_set_sweeps(mb4_state* s, int32_t sweeps) {
     return fail(MB4_EINVAL, "sweeps must be in [1, %d]", kMaxSweeps);
   if (s->fp32 && sweeps > mb4::kMaxFusedSweeps)
     return fail(MB4_EINVAL, "FP32 inner solves take at most %d sweeps", mb4::kMaxFusedSweeps);
+  if (sweeps > mb4::kMaxFusedSweeps) {
+    int prc = use_device(s);
+    if (prc == MB4_OK) prc = ensure_plain_fields(s);
+    if (prc != MB4_OK) return prc;
+  }
   if (sweeps != s->sweeps) drop_graphs(s);
   s->sweeps = sweeps;
   return MB4_OK;
@@ -1139,6 +1181,7 @@ int mb4_stage_solve(mb4_state* s, const double* d_phibar, double* d_rbar, int32_
   if (sweeps < 1 || sweeps > kMaxSweeps)
     return fail(MB4_EINVAL, "sweeps must be in [1, %d]", kMaxSweeps);
   if ((rc = use_device(s)) != MB4_OK) return rc;
+  if (sweeps > mb4::kMaxFusedSweeps && (rc = ensure_plain_fields(s)) != MB4_OK) return rc;
   const Lattice L = lattice_of(s);
   const CPlanes3 ph = cplanes_of(d_phibar, s->sites);
   const Planes3 ext = planes_of(d_rbar, s->sites);
