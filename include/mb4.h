@@ -174,6 +174,32 @@ MB4_API int mb4_energy(mb4_state* state, double* H);
  * sum |psi|^4 is the participation ratio of Sec. 3.2. */
 MB4_API int mb4_energy_components(mb4_state* state, double out[6]);
 
+/* The six components of mb4_energy_components for a field given on the
+ * device, without a state and without allocating anything: for callers that
+ * cannot call hipMalloc (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The per-tile partial sums go to a
+ * fixed device array of the library (3 MiB on each GPU it runs on, held
+ * until the process ends), so the lattice may have at most 32768 tiles of
+ * 64 x 4 sites, ceil(nx/64) * ceil(ny/4) <= 32768 (8,388,608 sites of full
+ * tiles, e.g. 2048 x 4096); larger ones return MB4_EINVAL.
+ *  lattice, nonlinearity: host structs as for mb4_create.
+ *  d_potential, d_p, d_q: device arrays of nx*ny doubles (V, Re psi, Im psi),
+ *    read.
+ *  d_out: device array of 6 doubles, written: H, U_K, U_I, U_E, sum |psi|^2,
+ *    sum |psi|^4, the same values, bit for bit, as mb4_energy_components of a
+ *    state holding this field.
+ *  stream: hipStream_t the kernels are enqueued on (NULL: null stream).
+ * Unlike the other entry points it only enqueues: the results are in d_out
+ * once the stream reaches them.  Every call on one GPU uses that GPU's one
+ * array, which is fully overwritten before it is read, so calls whose work
+ * may overlap on one GPU (other streams, other host threads) race; order
+ * them on one stream.  The first call on a device looks up the array's
+ * address there.  Errors: MB4_EINVAL (before any device call), MB4_EDEVICE. */
+MB4_API int mb4_energy_components_noalloc(const mb4_lattice* lattice,
+                                          const mb4_nonlinearity* nonlinearity,
+                                          const double* d_potential, const double* d_p,
+                                          const double* d_q, double* d_out, void* stream);
+
 /* Changes the time step (finite, non-zero). */
 MB4_API int mb4_set_h(mb4_state* state, double h);
 

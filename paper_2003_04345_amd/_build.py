@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmb4.so")
 SOURCES = ["mb4_kernels.hip", "mb4_spectral.hip", "mb4_runtime.hip", "mb4_engine.hip",
-           "mb4_ensemble.hip", "mb4_server.hip"]
+           "mb4_ensemble.hip", "mb4_server.hip", "mb4_noalloc.hip"]
 ARCH = "gfx950"
 
 

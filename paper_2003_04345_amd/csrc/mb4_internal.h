@@ -220,6 +220,10 @@ hipError_t launch_deinterleave(const double2* in, double* p, double* q, int n,
 size_t energy_partials_count(int nx, int ny);
 hipError_t launch_energy(const Lattice& lat, double* partials, double* out,
                          hipStream_t stream);
+// The same with psi given as two device planes p, q of nx*ny doubles (lat.u0
+// unused).
+hipError_t launch_energy_planes(const Lattice& lat, const double* p, const double* q,
+                                double* partials, double* out, hipStream_t stream);
 // The same for every member of a Multi (block0 over energy tiles): out[6 m + k];
 // partials holds 12 doubles per block.
 hipError_t launch_energy_multi(const Lattice& lat, const Multi& mu, double* partials,

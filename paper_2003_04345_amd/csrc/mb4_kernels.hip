@@ -1133,10 +1133,27 @@ __device__ __forceinline__ DD dd_add(DD a, DD b) {
 
 constexpr int kEnergyParts = 6;
 
+// psi at a site: from the interleaved L.u0, or (kPlanes) from two planes p, q
+// of nx*ny doubles each.
+struct PsiPlanes {
+  const double* p;
+  const double* q;
+};
+
+template <bool kPlanes>
+__device__ __forceinline__ double2 psi_at(const Lattice& L, const PsiPlanes& pl, int site) {
+  if constexpr (kPlanes)
+    return make_double2(pl.p[site], pl.q[site]);
+  else
+    return L.u0[site];
+}
+
 // Per-block sums of the six energy terms; partials[(block*6 + k)*2 + {0,1}]
 // with block the XCD-remapped index, so that a member's blocks are
 // contiguous.
-__global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* partials, Multi mu) {
+template <bool kPlanes>
+__global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* partials, Multi mu,
+                                                          PsiPlanes pl) {
   __shared__ DD red[kEnergyParts][kTile];
   const int bl = xcd_block(blockIdx.x, gridDim.x);
   const Loc w = locate(mu, L, bl);
@@ -1147,9 +1164,11 @@ __global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* par
     const int site = c.y * nx + c.x;
     const int xl = c.x == 0 ? nx - 1 : c.x - 1, xr = c.x == nx - 1 ? 0 : c.x + 1;
     const int yd = c.y == 0 ? ny - 1 : c.y - 1, yu = c.y == ny - 1 ? 0 : c.y + 1;
-    const double2 u = L.u0[site];
-    const double2 a = L.u0[c.y * nx + xl], b = L.u0[c.y * nx + xr];
-    const double2 d = L.u0[yd * nx + c.x], e = L.u0[yu * nx + c.x];
+    const double2 u = psi_at<kPlanes>(L, pl, site);
+    const double2 a = psi_at<kPlanes>(L, pl, c.y * nx + xl);
+    const double2 b = psi_at<kPlanes>(L, pl, c.y * nx + xr);
+    const double2 d = psi_at<kPlanes>(L, pl, yd * nx + c.x);
+    const double2 e = psi_at<kPlanes>(L, pl, yu * nx + c.x);
     const double sp = (a.x + b.x) + (d.x + e.x);
     const double sq = (a.y + b.y) + (d.y + e.y);
     const double n = u.x * u.x + u.y * u.y;
@@ -1475,7 +1494,21 @@ size_t energy_partials_count(int nx, int ny) {
 
 hipError_t launch_energy(const Lattice& lat, double* partials, double* out, hipStream_t stream) {
   const int nb = tile_blocks(lat.nx, lat.ny);
-  hipLaunchKernelGGL(k_energy_partial, dim3(nb), dim3(kTile), 0, stream, lat, partials, Multi{});
+  hipLaunchKernelGGL(k_energy_partial<false>, dim3(nb), dim3(kTile), 0, stream, lat, partials,
+                     Multi{}, PsiPlanes{nullptr, nullptr});
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kTile), 0, stream,
+                     static_cast<const double*>(partials), nb, static_cast<const int*>(nullptr),
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_planes(const Lattice& lat, const double* p, const double* q,
+                                double* partials, double* out, hipStream_t stream) {
+  const int nb = tile_blocks(lat.nx, lat.ny);
+  hipLaunchKernelGGL(k_energy_partial<true>, dim3(nb), dim3(kTile), 0, stream, lat, partials,
+                     Multi{}, PsiPlanes{p, q});
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kTile), 0, stream,
@@ -1486,8 +1519,8 @@ hipError_t launch_energy(const Lattice& lat, double* partials, double* out, hipS
 
 hipError_t launch_energy_multi(const Lattice& lat, const Multi& mu, double* partials,
                                double* out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_energy_partial, dim3(mu.blocks), dim3(kTile), 0, stream, lat, partials,
-                     mu);
+  hipLaunchKernelGGL(k_energy_partial<false>, dim3(mu.blocks), dim3(kTile), 0, stream, lat,
+                     partials, mu, PsiPlanes{nullptr, nullptr});
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_energy_final, dim3(mu.count), dim3(kTile), 0, stream,

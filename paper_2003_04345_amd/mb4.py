@@ -86,6 +86,8 @@ _SIGNATURES = {
     "mb4_step": (c_int, [c_void_p, c_int64]),
     "mb4_energy": (c_int, [c_void_p, POINTER(c_double)]),
     "mb4_energy_components": (c_int, [c_void_p, POINTER(c_double)]),
+    "mb4_energy_components_noalloc": (c_int, [POINTER(mb4_lattice), POINTER(mb4_nonlinearity),
+                                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mb4_set_h": (c_int, [c_void_p, c_double]),
     "mb4_set_region": (c_int, [c_void_p, c_int32]),
     "mb4_region": (c_int32, [c_void_p]),
@@ -247,6 +249,18 @@ def mb4_energy_components(state) -> dict:
     _check(load_library().mb4_energy_components(state, out), "mb4_energy_components")
     keys = ("H", "U_K", "U_I", "U_E", "prob", "participation")
     return {k: out[i] for i, k in enumerate(keys)}
+
+
+def mb4_energy_components_noalloc(nx: int, ny: int, g: float, d_potential, d_p, d_q, d_out,
+                                  t_hop: float = 1.0, diag_shift: float = 0.0,
+                                  stream: int = 0) -> None:
+    """Enqueues the energy components of the device field (d_p, d_q) into the
+    device array d_out[6] on `stream`; allocates nothing."""
+    lat = mb4_lattice(int(nx), int(ny), float(t_hop), float(diag_shift))
+    nl = mb4_nonlinearity(float(g))
+    _check(load_library().mb4_energy_components_noalloc(
+        byref(lat), byref(nl), _dptr(d_potential), _dptr(d_p), _dptr(d_q), _dptr(d_out),
+        c_void_p(int(stream)) if stream else None), "mb4_energy_components_noalloc")
 
 
 def mb4_set_h(state, h: float) -> None:

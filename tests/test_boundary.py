@@ -404,3 +404,31 @@ def test_server_calls_reject_null(lib):
     assert lib.mb4_server_stats(None, None) == M.MB4_EINVAL
     assert lib.mb4_server_clock(None) == -1.0
     lib.mb4_server_destroy(None)
+
+
+def test_noalloc_energy_validates_before_any_device_call(lib):
+    # Non-NULL stand-ins for device pointers: every call below is rejected on
+    # the host, so none of them is dereferenced.
+    fake = ctypes.c_void_p(256)
+    nl = M.mb4_nonlinearity(1.0)
+
+    def call(lat, nonlin=nl, ptrs=(fake, fake, fake, fake)):
+        return lib.mb4_energy_components_noalloc(
+            ctypes.byref(lat) if lat is not None else None,
+            ctypes.byref(nonlin) if nonlin is not None else None, *ptrs, None)
+
+    ok = M.mb4_lattice(64, 64, 1.0, 0.0)
+    assert call(None) == M.MB4_EINVAL
+    assert call(ok, nonlin=None) == M.MB4_EINVAL
+    for k in range(4):
+        ptrs = [fake] * 4
+        ptrs[k] = None
+        assert call(ok, ptrs=tuple(ptrs)) == M.MB4_EINVAL
+    assert call(M.mb4_lattice(2, 64, 1.0, 0.0)) == M.MB4_EINVAL
+    assert call(M.mb4_lattice(64, 64, float("nan"), 0.0)) == M.MB4_EINVAL
+    assert call(ok, nonlin=M.mb4_nonlinearity(float("inf"))) == M.MB4_EINVAL
+    # One tile row beyond the 32768 tiles of the scratch array (2048 x 4096
+    # is exactly 32768 tiles of 64 x 4).
+    assert call(M.mb4_lattice(2048, 4100, 1.0, 0.0)) == M.MB4_EINVAL
+    assert "scratch" in M.error_detail()
+    assert call(M.mb4_lattice(2049, 4096, 1.0, 0.0)) == M.MB4_EINVAL
