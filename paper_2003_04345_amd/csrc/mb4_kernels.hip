@@ -1131,6 +1131,37 @@ __device__ __forceinline__ DD dd_add(DD a, DD b) {
   return DD{hi, e - (hi - s)};
 }
 
+// Error-free product: a * b = hi + lo exactly (one FMA).
+__device__ __forceinline__ DD two_prod(double a, double b) {
+  const double p = a * b;
+  return DD{p, fma(a, b, -p)};
+}
+
+// Error-free sum (Knuth): a + b = hi + lo exactly.
+__device__ __forceinline__ DD two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return DD{s, (a - (s - bb)) + (b - bb)};
+}
+
+// x * c and x * y to about twice the working precision.
+__device__ __forceinline__ DD dd_mul(DD x, double c) {
+  const DD p = two_prod(x.hi, c);
+  const double e = p.lo + x.lo * c;
+  const double hi = p.hi + e;
+  return DD{hi, e - (hi - p.hi)};
+}
+
+__device__ __forceinline__ DD dd_mul(DD x, DD y) {
+  const DD p = two_prod(x.hi, y.hi);
+  const double e = p.lo + (x.hi * y.lo + x.lo * y.hi);
+  const double hi = p.hi + e;
+  return DD{hi, e - (hi - p.hi)};
+}
+
+// x * 2^k (exact).
+__device__ __forceinline__ DD dd_scale(DD x, double pow2) { return DD{x.hi * pow2, x.lo * pow2}; }
+
 constexpr int kEnergyParts = 6;
 
 // psi at a site: from the interleaved L.u0, or (kPlanes) from two planes p, q
@@ -1159,8 +1190,16 @@ __global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* par
   const Loc w = locate(mu, L, bl);
   const int nx = L.nx, ny = L.ny;
   const TileCoord c = tile_coord_at(nx, ny, w.b);
-  double v[kEnergyParts] = {0, 0, 0, 0, 0, 0};
+  DD v[kEnergyParts];
+#pragma unroll
+  for (int k = 0; k < kEnergyParts; ++k) v[k] = DD{0.0, 0.0};
   if (c.inside) {
+    // Each site's terms are formed in double-double from the exact inputs,
+    // so no rounding is left at the size of the terms themselves.  That
+    // matters where they cancel: with a diagonal shift 4t (the continuum
+    // -Delta_h), shift * n and t * (u . sum of neighbours) are both about
+    // 4 t n for a smooth field, and their difference, the kinetic energy
+    // density, is far smaller.
     const int site = c.y * nx + c.x;
     const int xl = c.x == 0 ? nx - 1 : c.x - 1, xr = c.x == nx - 1 ? 0 : c.x + 1;
     const int yd = c.y == 0 ? ny - 1 : c.y - 1, yu = c.y == ny - 1 ? 0 : c.y + 1;
@@ -1169,21 +1208,23 @@ __global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* par
     const double2 b = psi_at<kPlanes>(L, pl, c.y * nx + xr);
     const double2 d = psi_at<kPlanes>(L, pl, yd * nx + c.x);
     const double2 e = psi_at<kPlanes>(L, pl, yu * nx + c.x);
-    const double sp = (a.x + b.x) + (d.x + e.x);
-    const double sq = (a.y + b.y) + (d.y + e.y);
-    const double n = u.x * u.x + u.y * u.y;
-    const double uk = 0.5 * (L.shift * n - L.t * (u.x * sp + u.y * sq));
-    const double ue = 0.5 * L.V[site] * n;
-    const double ui = 0.25 * L.g * n * n;
-    v[0] = uk + ue + ui;
+    const DD sp = dd_add(two_sum(a.x, b.x), two_sum(d.x, e.x));
+    const DD sq = dd_add(two_sum(a.y, b.y), two_sum(d.y, e.y));
+    const DD n = dd_add(two_prod(u.x, u.x), two_prod(u.y, u.y));
+    const DD hop = dd_add(dd_mul(sp, u.x), dd_mul(sq, u.y));
+    const DD uk = dd_scale(dd_add(dd_mul(n, L.shift), dd_mul(hop, -L.t)), 0.5);
+    const DD ue = dd_scale(dd_mul(n, L.V[site]), 0.5);
+    const DD n2 = dd_mul(n, n);
+    const DD ui = dd_scale(dd_mul(n2, L.g), 0.25);
+    v[0] = dd_add(dd_add(uk, ue), ui);
     v[1] = uk;
     v[2] = ui;
     v[3] = ue;
     v[4] = n;
-    v[5] = n * n;
+    v[5] = n2;
   }
 #pragma unroll
-  for (int k = 0; k < kEnergyParts; ++k) red[k][threadIdx.x] = DD{v[k], 0.0};
+  for (int k = 0; k < kEnergyParts; ++k) red[k][threadIdx.x] = v[k];
   __syncthreads();
   for (int span = kTile / 2; span > 0; span >>= 1) {
     if (threadIdx.x < span) {

@@ -54,9 +54,10 @@ def test_continuum70_conserves_energy_and_probability():
     # iteration at h = 0.01 stops converging at t = 0.87 in the oracle too.
     # The tolerance is 1e-13 relative to ||u_0||_inf: evaluating the residual
     # with h ||K|| ~ 10 and |u| >= 5 leaves a rounding floor of about 3e-13.
-    # The accepted update may then be up to 5e-13, and the energy drifts by
-    # about 2e-14 over the run (the oracle's exact solves usually land further
-    # below the tolerance: 2e-15).
+    # The energy itself is evaluated with error-free per-site terms: with the
+    # diagonal shift 4t each site's terms cancel to the much smaller kinetic
+    # density, and a plain FP64 evaluation alone put about 2e-14 of rounding
+    # into the logged drift.
     torch_cuda()
     cfg = L.CONFIGS["continuum70"]
     v, p, q = L.make_inputs(cfg)
@@ -70,7 +71,7 @@ def test_continuum70_conserves_energy_and_probability():
             worst_h = max(worst_h, abs(c["H"] - c0["H"]) / abs(c0["H"]))
             worst_p = max(worst_p, abs(c["prob"] - c0["prob"]) / c0["prob"])
     print(f"continuum70, 50 steps: energy drift {worst_h:.3e}, probability drift {worst_p:.3e}")
-    assert worst_h <= 5e-14
+    assert worst_h <= 1e-14
     assert worst_p <= 1e-7
 
 
