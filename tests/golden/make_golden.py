@@ -35,9 +35,9 @@ CASES = {
     "lattice256": (1000, 1e-13, "gmres", 100, True),
     "lattice2048": (20, 1e-13, "gmres", 5, True),
     # The continuum runs of Sec. 3: the whole t in [0, 0.5] of the 70 x 70
-    # comparison run, and the first 200 steps (t = 2) of the delta run.
+    # comparison run, and the whole t in [0, 20] of the delta run.
     "continuum70": (50, 1e-13, "direct", 5, True),
-    "delta100": (200, 1e-13, "direct", 25, True),
+    "delta100": (2000, 1e-13, "direct", 125, True),
 }
 # Runs whose stopping test is relative to ||u_0||_inf (|u| reaches 5 there,
 # and the residual's rounding floor lies above the absolute 1e-13).
