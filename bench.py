@@ -211,10 +211,39 @@ def run_ensemble(args, torch, M) -> int:
                            "achieved_GBs": step_bytes / (elapsed / steps) / 1e9,
                            "peak_GBs": HBM_PEAK_GBS},
     }
+    if not args.no_plain_rates:
+        result["vs_plain"] = plain_rates(M, torch, result["value"], args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_member(args.cpu_member_steps)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def plain_rate(M, torch, cfg, steps: int, warm: int = 32) -> float:
+    """lattice-site-steps/s of one plain state (library defaults) on cfg,
+    timed over `steps` graph-replayed steps after `warm` untimed ones."""
+    v, p, q = L.make_inputs(cfg)
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h) as st:
+        st.set_state(p, q)
+        if st.step(warm) != M.MB4_OK:
+            raise RuntimeError(f"plain warm-up on {cfg.name}: {M.error_detail()}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if st.step(steps) != M.MB4_OK:
+            raise RuntimeError(f"plain run on {cfg.name}: {M.error_detail()}")
+        torch.cuda.synchronize()
+        return cfg.sites * steps / (time.perf_counter() - t0)
+
+
+def plain_rates(M, torch, value: float, args) -> dict:
+    """The ensemble's rate against the plain form on the same GPU: the
+    2048^2 lattice (the rate the batched form is to reach three times) and
+    one 128^2 realisation alone (the like-for-like single-lattice rate)."""
+    r2048 = plain_rate(M, torch, L.CONFIGS["lattice2048"], 200)
+    r128 = plain_rate(M, torch, L.ensemble_member(0), 320)
+    return {"lattice2048_site_steps_per_s": r2048, "ratio_to_lattice2048": value / r2048,
+            "single128_site_steps_per_s": r128, "ratio_to_single128": value / r128,
+            "target_ratio_to_lattice2048": 3.0, "target_met": value / r2048 >= 3.0}
 
 
 def serve_trace(M, torch, args, trace, inputs) -> dict:
@@ -450,6 +479,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=1024)
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--no-plain-rates", action="store_true",
+                    help="ensemble: skip the plain 2048^2 and single-128^2 comparison runs")
     ap.add_argument("--oracle-prefix-steps", type=int, default=2,
                     help="serving: steps of the larger requests compared with the oracle")
     ap.add_argument("--oracle-workers", type=int, default=16,

@@ -69,6 +69,11 @@ struct Engine {
   MemberDesc* d_desc = nullptr;
   int* d_block0 = nullptr;  // 4 prefix tables of max_members + 1
   int blocks[4] = {0, 0, 0, 0};
+  // Block -> member tables of the 4 classes, one after the other from
+  // member_of_at[c], filled on the device from d_block0.
+  int* d_member_of = nullptr;
+  size_t member_of_cap = 0;
+  size_t member_of_at[4] = {0, 0, 0, 0};
   int* d_todo = nullptr;
   int* h_todo = nullptr;
   unsigned long long* ring = nullptr;    // [kBatch][max_members][rec_len]
@@ -142,6 +147,27 @@ int upload_blocks(Engine* e) {
   }
   for (int c = 0; c < 4; ++c) e->blocks[c] = tab[size_t(c) * stride + n];
   HIP_TRY(hipMemcpy(e->d_block0, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+  // Block -> member tables, so that a block of a launch finds its member with
+  // one load instead of a binary search over the members.
+  size_t total = 0;
+  for (int c = 0; c < 4; ++c) {
+    e->member_of_at[c] = total;
+    total += size_t(e->blocks[c]);
+  }
+  if (total > e->member_of_cap) {
+    if (e->d_member_of != nullptr) {
+      (void)hipFree(e->d_member_of);
+      e->allocs.erase(std::find(e->allocs.begin(), e->allocs.end(), e->d_member_of));
+      e->d_member_of = nullptr;
+      e->member_of_cap = 0;
+    }
+    const int rc = dalloc(e, reinterpret_cast<void**>(&e->d_member_of), sizeof(int) * total);
+    if (rc != MB4_OK) return rc;
+    e->member_of_cap = total;
+  }
+  for (int c = 0; c < 4; ++c)
+    HIP_TRY(launch_member_table(e->d_block0 + size_t(c) * stride, n, e->blocks[c],
+                                e->d_member_of + e->member_of_at[c], e->cfg.stream));
   if (size_t(e->blocks[kEnergy]) > e->partials_blocks) {
     if (e->partials != nullptr) {
       (void)hipFree(e->partials);
@@ -163,6 +189,7 @@ Multi multi_of(const Engine* e, int cls, int step) {
   Multi mu;
   mu.desc = e->d_desc;
   mu.block0 = e->d_block0 + size_t(cls) * (e->cfg.max_members + 1);
+  mu.member_of = e->d_member_of + e->member_of_at[cls];
   mu.count = int(e->desc.size());
   mu.blocks = e->blocks[cls];
   mu.todo = e->d_todo;

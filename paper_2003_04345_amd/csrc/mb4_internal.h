@@ -54,7 +54,8 @@ struct ConvCheck {
 // Several independent lattices ("members") advanced by the same launches.
 // Member m's sites are [base, base + nx*ny) of ensemble-wide fields, whose
 // planes are all members' sites long; its step record starts rec_stride words
-// after member m-1's.  A block finds its member by binary search in block0.
+// after member m-1's.  A block finds its member in member_of (one load), or
+// by binary search in block0 when there is no such table.
 struct MemberDesc {
   int nx, ny;
   double t, shift, g, h;
@@ -64,6 +65,7 @@ struct MemberDesc {
 struct Multi {
   const MemberDesc* desc = nullptr;  // device [count]; NULL: the Lattice argument alone
   const int* block0 = nullptr;       // device [count + 1]: first block of each member
+  const int* member_of = nullptr;    // device [blocks]: member of each block (or NULL)
   int count = 0;
   int blocks = 0;                    // blocks of the launch (block0[count])
   const int* todo = nullptr;         // device [count]: steps of the batch each member takes
@@ -93,6 +95,11 @@ struct LaunchEvents {
 // Kernel launchers (each enqueues on `stream`; return hipSuccess or an error).
 // p[0 .. n) = 0 (a kernel, so that it may sit in a captured graph).
 hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream);
+
+// member_of[b] = m for every block b in [block0[m], block0[m + 1]), m < count,
+// b < blocks = block0[count] (the table Multi::member_of points into).
+hipError_t launch_member_table(const int* block0, int count, int blocks, int* member_of,
+                               hipStream_t stream);
 
 // The launchers below that take a Multi run every member of it when mu.desc is
 // not NULL: the Lattice then carries ensemble-wide V and u0, planes and

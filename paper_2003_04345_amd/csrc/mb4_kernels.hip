@@ -138,15 +138,21 @@ struct Loc {
   bool skip;
 };
 
+// The member whose blocks [block0[m], block0[m + 1]) hold block b.
+__device__ __forceinline__ int member_search(const int* block0, int count, int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (block0[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ Loc locate(const Multi& mu, Lattice& L, int b) {
   Loc w{b, 0, 0, 0, false};
   if (mu.desc == nullptr) return w;
-  int lo = 0, hi = mu.count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (mu.block0[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = mu.member_of != nullptr ? mu.member_of[b] : member_search(mu.block0, mu.count, b);
   const MemberDesc d = mu.desc[lo];
   w.b = b - mu.block0[lo];
   w.m = lo;
@@ -234,6 +240,12 @@ __device__ __forceinline__ double2 t_apply(int j, const double2 (&r)[3]) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_clear_u64(unsigned long long* p, int n) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_member_table(const int* block0, int count, int blocks,
+                                                      int* member_of) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < blocks) member_of[b] = member_search(block0, count, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1316,6 +1328,13 @@ int tile_blocks(int nx, int ny) {
 hipError_t launch_clear(unsigned long long* p, int n, hipStream_t stream) {
   const int blocks = std::max(1, std::min((n + 255) / 256, 64));
   MB4_LAUNCH(k_clear_u64, dim3(blocks), dim3(256), LaunchEvents{}, p, n);
+}
+
+hipError_t launch_member_table(const int* block0, int count, int blocks, int* member_of,
+                               hipStream_t stream) {
+  if (blocks <= 0) return hipSuccess;
+  MB4_LAUNCH(k_member_table, dim3((blocks + 255) / 256), dim3(256), LaunchEvents{}, block0, count,
+             blocks, member_of);
 }
 
 hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout, CPlanes3 rbar,
