@@ -429,11 +429,15 @@ __device__ __forceinline__ SiteBlock site_block(const Lattice& L, double2 u, dou
   return s;
 }
 
-// r = (I - hl J_site)^-1 b, given inv = 1 / det(I - hl J_site).
+// r = (I - hl J_site)^-1 b, given inv = 1 / det(I - hl J_site).  The inverse
+// is inv * (I + hl J'), J' = [[a, bb], [-cc, -a]], applied as
+// inv * (b + hl J' b): no product of hl with the site block is formed, so
+// nothing per stage has to be kept across the sweeps.
 __device__ __forceinline__ double2 block_solve(const SiteBlock& s, double hl, double inv, double bp,
                                                double bq) {
-  return make_double2(inv * ((1.0 + hl * s.a) * bp + hl * s.bb * bq),
-                      inv * ((1.0 - hl * s.a) * bq - hl * s.cc * bp));
+  const double jp = s.a * bp + s.bb * bq;
+  const double jq = s.cc * bp + s.a * bq;
+  return make_double2(inv * (bp + hl * jp), inv * (bq - hl * jq));
 }
 
 // Precision of the stage corrections and of the sweeps: RT = double, or
@@ -476,8 +480,9 @@ __device__ __forceinline__ SiteBlockT<T> block_in(const SiteBlock& s) {
 template <class T>
 __device__ __forceinline__ vec2_t<T> block_solve_t(const SiteBlockT<T>& s, T hl, T inv, T bp,
                                                    T bq) {
-  return vec2<T>(inv * ((T(1) + hl * s.a) * bp + hl * s.bb * bq),
-                 inv * ((T(1) - hl * s.a) * bq - hl * s.cc * bp));
+  const T jp = s.a * bp + s.bb * bq;
+  const T jq = s.cc * bp + s.a * bq;
+  return vec2<T>(inv * (bp + hl * jp), inv * (bq - hl * jq));
 }
 
 // 1 / det(I - h lambda_i J_site) for the three stages, d_i = 1 +
