@@ -30,6 +30,7 @@ STREAM_DISORDER = 0
 STREAM_DEFECTS = 1
 STREAM_AMPLITUDE = 2
 STREAM_PHASE = 3
+STREAM_NONLINEARITY = 4
 
 
 def _mix64(z: np.ndarray) -> np.ndarray:
@@ -89,6 +90,8 @@ class LatticeProblem:
     origin_v: float | None = None  # potential at site 0 (the grid origin), if set
     centre: tuple | None = None    # wavepacket centre (x, y); None: (nx // 2, ny // 2)
     amp_range: tuple = (0.1, 0.5)  # "random": |psi_j| ~ Uniform[lo, hi]
+    g_range: tuple | None = None   # per-site nonlinearity g_j ~ Uniform[lo, hi]
+                                   # (stream 4) in place of g, if set
     extra: dict = field(default_factory=dict)
 
     @property
@@ -165,6 +168,16 @@ def make_random_field(prob: LatticeProblem) -> tuple[np.ndarray, np.ndarray]:
     amp = lo + (hi - lo) * draw_uniform(prob.seed, STREAM_AMPLITUDE, prob.sites)
     ph = 2.0 * math.pi * draw_uniform(prob.seed, STREAM_PHASE, prob.sites)
     return amp * np.cos(ph), amp * np.sin(ph)
+
+
+def make_nonlinearity(prob: LatticeProblem) -> np.ndarray | None:
+    """Per-site nonlinearity g_j (length nx*ny), i.i.d. Uniform[lo, hi] from
+    stream 4, when the problem has a g_range; None for the uniform g."""
+    if prob.g_range is None:
+        return None
+    lo, hi = prob.g_range
+    return np.ascontiguousarray(lo + (hi - lo) * draw_uniform(prob.seed, STREAM_NONLINEARITY,
+                                                               prob.sites))
 
 
 def make_inputs(prob: LatticeProblem) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

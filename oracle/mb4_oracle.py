@@ -192,7 +192,12 @@ def hopping_matrix(nx: int, ny: int, t_hop: float, diag_shift: float = 0.0) -> s
 
 
 class LatticeNLS:
-    """i psi' = (K + V) psi + g |psi|^2 psi on an nx x ny periodic lattice."""
+    """i psi' = (K + V) psi + g |psi|^2 psi on an nx x ny periodic lattice.
+
+    g is one number, or one per site: the site-dependent nonlinearity of the
+    Appendix, U_I = -1/2 sum_i gamma_i n_i^2 (gamma_i = -g_i), for which the
+    energy U_K + U_E + U_I is conserved all the same.
+    """
 
     def __init__(self, nx, ny, potential, g, t_hop=1.0, diag_shift=0.0):
         if nx < 3 or ny < 3:
@@ -200,7 +205,10 @@ class LatticeNLS:
         self.nx, self.ny = int(nx), int(ny)
         self.s = self.nx * self.ny
         self.v = np.asarray(potential, dtype=np.float64).reshape(self.s)
-        self.g = float(g)
+        if np.ndim(g) == 0:
+            self.g = float(g)
+        else:
+            self.g = np.asarray(g, dtype=np.float64).reshape(self.s).copy()
         self.gamma = -self.g                     # paper's gamma (Eq. dNLS)
         self.t_hop = float(t_hop)
         self.diag_shift = float(diag_shift)
@@ -237,7 +245,10 @@ class LatticeNLS:
         ui_terms = n * n
         uk = 0.5 * math.fsum(uk_terms.tolist())
         ue = 0.5 * math.fsum(ue_terms.tolist())
-        ui = 0.25 * self.g * math.fsum(ui_terms.tolist())
+        if np.ndim(self.g) == 0:
+            ui = 0.25 * self.g * math.fsum(ui_terms.tolist())
+        else:
+            ui = 0.25 * math.fsum((self.g * ui_terms).tolist())
         h_total = 0.5 * math.fsum(np.concatenate(
             [uk_terms, ue_terms, 0.5 * self.g * ui_terms]).tolist())
         return {"H": h_total, "U_K": uk, "U_I": ui, "U_E": ue,
@@ -381,9 +392,10 @@ def energy_drift(energies) -> float:
 
 
 def oracle_for(prob_cfg, potential, eps=EPS_PAPER, max_newton=50, solver="direct",
-               constants=None, relative=False) -> MB4Oracle:
-    """Oracle for a lattice_inputs.LatticeProblem-like object."""
-    lat = LatticeNLS(prob_cfg.nx, prob_cfg.ny, potential, prob_cfg.g,
+               constants=None, relative=False, g=None) -> MB4Oracle:
+    """Oracle for a lattice_inputs.LatticeProblem-like object; g (one value
+    per site) replaces the problem's uniform g when given."""
+    lat = LatticeNLS(prob_cfg.nx, prob_cfg.ny, potential, prob_cfg.g if g is None else g,
                      t_hop=prob_cfg.t_hop, diag_shift=prob_cfg.diag_shift)
     return MB4Oracle(lat, prob_cfg.h, eps=eps, max_newton=max_newton,
                      solver=solver, constants=constants, relative=relative)

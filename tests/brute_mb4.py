@@ -120,10 +120,11 @@ def collocation_step(f, u0, h, alpha1=mpmath.mpf(-1425) / 2,
 
 def lattice_f(nx, ny, t_hop, v, g):
     """f(psi) = -i((K + V) psi + g |psi|^2 psi), K = -t on periodic links,
-    written out site by site from the lattice definition."""
+    written out site by site from the lattice definition; g is one number
+    or a list with one per site."""
     v = [mpmath.mpf(x) for x in v]
     t_hop = mpmath.mpf(t_hop)
-    g = mpmath.mpf(g)
+    gs = [mpmath.mpf(x) for x in g] if isinstance(g, (list, tuple)) else [mpmath.mpf(g)] * len(v)
 
     def f(psi):
         out = []
@@ -134,6 +135,6 @@ def lattice_f(nx, ny, t_hop, v, g):
                       + psi[((y + 1) % ny) * nx + x] + psi[((y - 1) % ny) * nx + x])
                 a_psi = -t_hop * nb + v[k] * psi[k]
                 n_k = mpmath.re(psi[k]) ** 2 + mpmath.im(psi[k]) ** 2
-                out.append(-1j * (a_psi + g * n_k * psi[k]))
+                out.append(-1j * (a_psi + gs[k] * n_k * psi[k]))
         return out
     return f
