@@ -200,6 +200,16 @@ MB4_API int mb4_energy_components_noalloc(const mb4_lattice* lattice,
                                           const double* d_potential, const double* d_p,
                                           const double* d_q, double* d_out, void* stream);
 
+/* Site-dependent nonlinearity (the Appendix's U_I = -1/2 sum_i gamma_i n_i^2,
+ * here g_i = -gamma_i): the flow becomes i psi_j' = ((K + V) psi)_j +
+ * g_j |psi_j|^2 psi_j, and H's U_I = 1/4 sum_j g_j |psi_j|^4, which MB4
+ * conserves as before.  g: host array of nx*ny finite doubles (copied), or
+ * NULL to return to the uniform g of mb4_create.  The first call allocates
+ * 8 bytes per site of device memory within mem_budget.  Single states only;
+ * the ensemble and server keep one g per member.  Errors: MB4_EINVAL,
+ * MB4_ENOMEM, MB4_EDEVICE. */
+MB4_API int mb4_set_nonlinearity_sites(mb4_state* state, const double* g);
+
 /* Changes the time step (finite, non-zero). */
 MB4_API int mb4_set_h(mb4_state* state, double h);
 

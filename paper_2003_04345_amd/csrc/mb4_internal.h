@@ -17,12 +17,14 @@ constexpr int kMaxNewton = 1000;
 // patterns sort above +inf, survives it).
 
 // The lattice problem as the kernels see it: periodic nx x ny, hopping -t on
-// the four links, on-site A_jj = V_j + shift, nonlinearity g, time step h.
+// the four links, on-site A_jj = V_j + shift, nonlinearity g (or g_j per
+// site), time step h.
 struct Lattice {
   int nx, ny;
   double t, shift, g, h;
   const double* V;     // [nx*ny]
   const double2* u0;   // [nx*ny] (p, q)
+  const double* gs = nullptr;  // [nx*ny] g_j per site, or NULL: g at every site
 };
 
 // Three planes of a stage field (element type double2, or float2 for the

@@ -128,6 +128,11 @@ __device__ __forceinline__ bool converged_at(const ConvCheck& c) {
   return r <= (c.relative ? conv_tol(c.eps, bits_double(c.rec[0])) : c.eps);
 }
 
+// The nonlinearity g at a site: its own g_j, or the lattice's g.
+__device__ __forceinline__ double site_g(const Lattice& L, int site) {
+  return L.gs != nullptr ? L.gs[site] : L.g;
+}
+
 // Where block b (after xcd_block) works: for a Multi, its member's lattice
 // replaces L (with V and u0 moved to the member's sites), b becomes the block
 // index within the member, and `base` / `rec` are the member's site and
@@ -167,6 +172,7 @@ __device__ __forceinline__ Loc locate(const Multi& mu, Lattice& L, int b) {
   L.h = d.h;
   L.V += d.base;
   L.u0 += d.base;
+  if (L.gs != nullptr) L.gs += d.base;
   return w;
 }
 
@@ -356,7 +362,7 @@ __global__ __launch_bounds__(kTile) void k_update_residual(Lattice L, CPlanes3 U
   __syncthreads();
 
   if (c.inside) {
-    const double t = L.t, g = L.g, h = L.h;
+    const double t = L.t, g = site_g(L, site), h = L.h;
     const double vs = L.V[site] + L.shift;
     double2 phi[3];
     // Linear part: int A_{c_i,z} (f_K + f_E)(U_z) dz = S A W_i (Eq. fKu2).
@@ -419,13 +425,13 @@ struct SiteBlock {
   double a, bb, cc;
 };
 
-__device__ __forceinline__ SiteBlock site_block(const Lattice& L, double2 u, double v) {
+__device__ __forceinline__ SiteBlock site_block(const Lattice& L, double2 u, double v, double g) {
   const double vs = v + L.shift;
   const double pp = u.x * u.x, qq = u.y * u.y;
   SiteBlock s;
-  s.a = 2.0 * L.g * u.x * u.y;
-  s.bb = vs + L.g * (pp + 3.0 * qq);
-  s.cc = vs + L.g * (3.0 * pp + qq);
+  s.a = 2.0 * g * u.x * u.y;
+  s.bb = vs + g * (pp + 3.0 * qq);
+  s.cc = vs + g * (3.0 * pp + qq);
   return s;
 }
 
@@ -514,12 +520,12 @@ __device__ __forceinline__ void block_invs(const SiteBlockT<T>& s, double h, T (
 
 // f(u_0) = S grad H = (A q + g n q, -(A p + g n p)) at one site, from u and
 // its four neighbours a, b (x -/+ 1), d, e (y -/+ 1).
-__device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v, double2 a,
-                                          double2 b, double2 d, double2 e) {
+__device__ __forceinline__ double2 f_from(const Lattice& L, double2 u, double v, double g,
+                                          double2 a, double2 b, double2 d, double2 e) {
   const double sp = (a.x + b.x) + (d.x + e.x);
   const double sq = (a.y + b.y) + (d.y + e.y);
   const double vs = v + L.shift;
-  const double gn = L.g * (u.x * u.x + u.y * u.y);
+  const double gn = g * (u.x * u.x + u.y * u.y);
   return make_double2(-L.t * sq + (vs + gn) * u.y, L.t * sp - (vs + gn) * u.x);
 }
 
@@ -648,13 +654,14 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   // Own positions first: their potential is loaded before the u_0 staging
   // below, so both sets of loads are in flight together.
   int gsite[PER];
-  double vv[PER];
+  double vv[PER], gg[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kSolveThreads;
     const int lx = idx % RX, ly = idx / RX;
     gsite[j] = wrap_in(ty0 - H + ly, ny, fast) * nx + wrap_in(tx0 - H + lx, nx, fast);
     vv[j] = L.V[gsite[j]];
+    gg[j] = site_g(L, gsite[j]);
   }
   if (FIRST) {
     // All loads of the staging first, then the stores, so that the rounds'
@@ -691,11 +698,11 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
     const int e = (ly + 1) * UX + lx + 1;
     const double2 u = FIRST ? su[e] : L.u0[site];
     const double v = vv[j];
-    blk[j] = block_in<RT>(site_block(L, u, v));
+    blk[j] = block_in<RT>(site_block(L, u, v, gg[j]));
     block_invs(blk[j], L.h, inv[j]);
     double2 f = make_double2(0.0, 0.0);
     if (FIRST) {
-      f = f_from(L, u, v, su[e - 1], su[e + 1], su[e - UX], su[e + UX]);
+      f = f_from(L, u, v, gg[j], su[e - 1], su[e + 1], su[e - UX], su[e + UX]);
       const bool tile = lx >= H && lx < H + TSX && ly >= H && ly < H + TSY &&
                         tx0 + lx - H < nx && ty0 + ly - H < ny;
       if (tile) {
@@ -882,7 +889,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   int gsite[PER];
   double2 u0v[PER];
   double2 xv[PER][3];
-  double vv[PER];
+  double vv[PER], gg[PER];
   // Phase 1: W_i on the whole region.  Every load of both positions is
   // issued before the first LDS store, so that their latencies overlap.
 #pragma unroll
@@ -893,6 +900,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
     gsite[j] = site;
     u0v[j] = L.u0[site];
     vv[j] = L.V[site];
+    gg[j] = site_g(L, site);
 #pragma unroll
     for (int i = 0; i < 3; ++i) xv[j][i] = Xin.s[i][site];
   }
@@ -924,10 +932,10 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   for (int j = 0; j < PER; ++j) {
     const int idx = threadIdx.x + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
-    blk[j] = block_in<RT>(site_block(L, u0v[j], vv[j]));
+    blk[j] = block_in<RT>(site_block(L, u0v[j], vv[j], gg[j]));
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
       block_invs(blk[j], L.h, inv[j]);
-      const double t = L.t, g = L.g, h = L.h;
+      const double t = L.t, g = gg[j], h = L.h;
       const double vs = vv[j] + L.shift;
       double2 phi[3];
 #pragma unroll
@@ -1105,7 +1113,7 @@ __global__ __launch_bounds__(kTile) void k_stage_sweep(Lattice L, CPlanes3 phib,
   unsigned long long rm = 0ull;
   if (c.inside) {
     const int site = c.y * nx + c.x;
-    const SiteBlock blk = site_block(L, L.u0[site], L.V[site]);
+    const SiteBlock blk = site_block(L, L.u0[site], L.V[site], site_g(L, site));
     const int xl = c.x == 0 ? nx - 1 : c.x - 1, xr = c.x == nx - 1 ? 0 : c.x + 1;
     const int yd = c.y == 0 ? ny - 1 : c.y - 1, yu = c.y == ny - 1 ? 0 : c.y + 1;
     const int sl = c.y * nx + xl, sr = c.y * nx + xr, sd = yd * nx + c.x, su = yu * nx + c.x;
@@ -1232,7 +1240,7 @@ __global__ __launch_bounds__(kTile) void k_energy_partial(Lattice L, double* par
     const DD uk = dd_scale(dd_add(dd_mul(n, L.shift), dd_mul(hop, -L.t)), 0.5);
     const DD ue = dd_scale(dd_mul(n, L.V[site]), 0.5);
     const DD n2 = dd_mul(n, n);
-    const DD ui = dd_scale(dd_mul(n2, L.g), 0.25);
+    const DD ui = dd_scale(dd_mul(n2, site_g(L, site)), 0.25);
     v[0] = dd_add(dd_add(uk, ue), ui);
     v[1] = uk;
     v[2] = ui;

@@ -124,6 +124,8 @@ struct mb4_state {
   std::vector<void*> device_allocs;
   std::vector<void*> host_allocs;
   double* V = nullptr;
+  double* gs = nullptr;    // per-site nonlinearity g_j, allocated on first use
+  bool gs_on = false;      // the kernels read gs instead of g
   double2* u0 = nullptr;
   double2* u0b = nullptr;  // second u_0 buffer of the fused path's batches
   double2* Ua[3] = {nullptr, nullptr, nullptr};
@@ -187,6 +189,13 @@ size_t footprint_bytes(size_t sites, int nx, int ny, int max_newton, bool plain)
          mb4::energy_partials_count(nx, ny) * sizeof(double) + 8 * sizeof(double);
 }
 
+// Device bytes of a state with (plain) the plain path's fields and (site_g)
+// a per-site nonlinearity.
+size_t state_bytes(const mb4_state* s, bool plain, bool site_g) {
+  return footprint_bytes(s->sites, s->nx, s->ny, s->max_newton, plain) +
+         (site_g ? s->sites * sizeof(double) : 0);
+}
+
 int dalloc(mb4_state* s, void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
@@ -202,8 +211,7 @@ int dalloc(mb4_state* s, void** p, size_t bytes) {
 // use within the state's memory budget.
 int ensure_plain_fields(mb4_state* s) {
   if (s->phib[0] != nullptr) return MB4_OK;
-  if (s->mem_budget != 0 &&
-      footprint_bytes(s->sites, s->nx, s->ny, s->max_newton, true) > s->mem_budget)
+  if (s->mem_budget != 0 && state_bytes(s, true, s->gs != nullptr) > s->mem_budget)
     return fail(MB4_ENOMEM, "the plain path needs %zu bytes per site more, above mem_budget %llu",
                 kPlainBytesPerSite, static_cast<unsigned long long>(s->mem_budget));
   const size_t field = s->sites * sizeof(double2);
@@ -264,6 +272,7 @@ Lattice lattice_of(const mb4_state* s) {
   L.h = s->h;
   L.V = s->V;
   L.u0 = s->u0;
+  L.gs = s->gs_on ? s->gs : nullptr;
   return L;
 }
 
@@ -949,6 +958,32 @@ int mb4_energy(mb4_state* s, double* H) {
   const int rc = mb4_energy_components(s, comp);
   if (rc == MB4_OK) *H = comp[0];
   return rc;
+}
+
+int mb4_set_nonlinearity_sites(mb4_state* s, const double* g) {
+  int rc = check_state(s);
+  if (rc != MB4_OK) return rc;
+  if (g == nullptr) {
+    if (s->gs_on) drop_graphs(s);
+    s->gs_on = false;
+    return MB4_OK;
+  }
+  if (!all_finite(g, s->sites)) return fail(MB4_EINVAL, "every g_j must be finite");
+  rc = use_device(s);
+  if (rc != MB4_OK) return rc;
+  if (s->gs == nullptr) {
+    if (s->mem_budget != 0 && state_bytes(s, s->phib[0] != nullptr, true) > s->mem_budget)
+      return fail(MB4_ENOMEM, "a per-site nonlinearity needs 8 bytes per site more, above "
+                  "mem_budget %llu", static_cast<unsigned long long>(s->mem_budget));
+    rc = dalloc(s, reinterpret_cast<void**>(&s->gs), s->sites * sizeof(double));
+    if (rc != MB4_OK) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(s->gs, g, s->sites * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  // Captured batches hold the lattice, and with it whether g_j is read.
+  drop_graphs(s);
+  s->gs_on = true;
+  return MB4_OK;
 }
 
 int mb4_set_h(mb4_state* s, double h) {

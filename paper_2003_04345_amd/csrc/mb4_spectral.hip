@@ -154,9 +154,10 @@ __global__ __launch_bounds__(kLineThreads) void k_spec_rows(Lattice L, CPlanes3 
         const double2 u = L.u0[site];
         const double pp = u.x * u.x, qq = u.y * u.y;
         const double dv = (L.V[site] + L.shift) - sa.kappa0;
-        const double ca = 2.0 * L.g * u.x * u.y;
-        const double db = dv + L.g * (pp + 3.0 * qq);
-        const double dc = dv + L.g * (3.0 * pp + qq);
+        const double g = L.gs != nullptr ? L.gs[site] : L.g;
+        const double ca = 2.0 * g * u.x * u.y;
+        const double db = dv + g * (pp + 3.0 * qq);
+        const double dc = dv + g * (3.0 * pp + qq);
         const double hl = L.h * MB4_LAMBDA[i];
         const double2 ph = phib.s[i][site];
         b[i][k] = make_double2(-ph.x + hl * (ca * rv.x + db * rv.y),

@@ -89,6 +89,7 @@ _SIGNATURES = {
     "mb4_energy_components_noalloc": (c_int, [POINTER(mb4_lattice), POINTER(mb4_nonlinearity),
                                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mb4_set_h": (c_int, [c_void_p, c_double]),
+    "mb4_set_nonlinearity_sites": (c_int, [c_void_p, POINTER(c_double)]),
     "mb4_set_region": (c_int, [c_void_p, c_int32]),
     "mb4_region": (c_int32, [c_void_p]),
     "mb4_set_sweeps": (c_int, [c_void_p, c_int32]),
@@ -263,6 +264,16 @@ def mb4_energy_components_noalloc(nx: int, ny: int, g: float, d_potential, d_p, 
         c_void_p(int(stream)) if stream else None), "mb4_energy_components_noalloc")
 
 
+def mb4_set_nonlinearity_sites(state, g, sites: int) -> None:
+    """g: nx*ny values g_j, or None for the state's uniform g."""
+    if g is None:
+        ptr = None
+    else:
+        arr = _host(g, sites)
+        ptr = arr.ctypes.data_as(POINTER(c_double))
+    _check(load_library().mb4_set_nonlinearity_sites(state, ptr), "mb4_set_nonlinearity_sites")
+
+
 def mb4_set_h(state, h: float) -> None:
     _check(load_library().mb4_set_h(state, float(h)), "mb4_set_h")
 
@@ -395,6 +406,9 @@ class MB4State:
 
     def energy_components(self) -> dict:
         return mb4_energy_components(self._h)
+
+    def set_nonlinearity_sites(self, g) -> None:
+        mb4_set_nonlinearity_sites(self._h, g, self.sites)
 
     def set_h(self, h: float) -> None:
         mb4_set_h(self._h, h)

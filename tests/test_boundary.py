@@ -432,3 +432,8 @@ def test_noalloc_energy_validates_before_any_device_call(lib):
     assert call(M.mb4_lattice(2048, 4100, 1.0, 0.0)) == M.MB4_EINVAL
     assert "scratch" in M.error_detail()
     assert call(M.mb4_lattice(2049, 4096, 1.0, 0.0)) == M.MB4_EINVAL
+
+
+def test_set_nonlinearity_sites_rejects_a_null_state(lib):
+    g = (ctypes.c_double * 9)(*([1.0] * 9))
+    assert lib.mb4_set_nonlinearity_sites(None, g) == M.MB4_EINVAL
