@@ -84,7 +84,8 @@ def test_workload_matches_stored_oracle_run(name, fp32_solve, tune):
 @pytest.mark.parametrize("name", ["continuum70", "delta100"])
 def test_continuum_workload_matches_stored_oracle_run(name):
     # The continuum runs of Sec. 3 against the oracle's direct stage solves:
-    # continuum70 over its whole t in [0, 0.5], delta100 over t in [0, 2].
+    # continuum70 over its whole t in [0, 0.5], delta100 over its whole
+    # t in [0, 20] (2000 steps).
     torch_cuda()
     g = _golden(name)
     every = g["energies"][1][0]
