@@ -652,8 +652,15 @@ def main(argv=None) -> int:
         result["observables"] = observables
         prof = {}  # small, cache-resident grids: no HBM roofline applies
     if prof:
-        dominant = max(prof, key=lambda k: prof[k][1])
-        n_launch, total_ms = prof[dominant]
+        # Iterations 1 and l >= 2 of the fused iteration are the same kernel
+        # (k_iterate); the roofline takes them together.
+        by_kernel = dict(prof)
+        if "iterate_first" in by_kernel and "iterate" in by_kernel:
+            n1, t1 = by_kernel.pop("iterate_first")
+            n2, t2 = by_kernel["iterate"]
+            by_kernel["iterate"] = (n1 + n2, t1 + t2)
+        dominant = max(by_kernel, key=lambda k: by_kernel[k][1])
+        n_launch, total_ms = by_kernel[dominant]
         per_launch_s = total_ms / 1e3 / max(n_launch, 1)
         bytes_launch = BYTES_PER_SITE[dominant] * sites
         achieved = bytes_launch / per_launch_s / 1e9
@@ -667,6 +674,10 @@ def main(argv=None) -> int:
             "traffic_frac": (None if traffic is None
                              else traffic / per_launch_s / 1e9 / HBM_PEAK_GBS),
         }
+        if args.workload == "lattice2048":
+            # The stated target on this lattice: 60% of the HBM peak.
+            result["hbm_target"] = {"frac_target": 0.6, "frac": achieved / HBM_PEAK_GBS,
+                                    "met": achieved / HBM_PEAK_GBS >= 0.6}
         result["kernel_time_ms"] = {k: {"launches": n, "total_ms": ms} for k, (n, ms) in prof.items()}
         result["kernel_timing_steps"] = prof_steps
     if not args.no_cpu_baseline:
