@@ -43,6 +43,10 @@ HBM_PEAK_GBS = 8000.0
 #   iterate_first, iterate: u0 16 + V 8 + X^l 48 -> X^{l+1} 48 (residual of
 #                          iteration l, the next stage solve and the update,
 #                          Phibar and rbar kept on chip)
+#   iterate_last:          u0 16 + V 8 + X^l 48 -> X^{l+1}_3 16 (the last
+#                          iteration of a batch's step: a step that does not
+#                          converge there is taken again from u0, so only
+#                          X_3, which u1 = u0 + X_3 takes, is written)
 #   final_update:          u0 16 + X_3 16 -> u1 16
 #   final_first:           u0 16 + X_3 16 + V 8 -> u1 16 + X^1 48 (the final
 #                          update of a step fused with the next step's first
@@ -62,6 +66,7 @@ BYTES_PER_SITE = {
     "final_update": 48,
     "iterate_first": 120,
     "iterate": 120,
+    "iterate_last": 88,
     "final_first": 104,
 }
 
@@ -139,7 +144,9 @@ def step_bytes_per_site(iters: int) -> int:
     the fused iterations (the first step's plain first solve and the last
     step's final update are not counted)."""
     b = BYTES_PER_SITE
-    return b["final_first"] + b["iterate"] * (iters - 1)
+    if iters < 2:
+        return b["final_first"]
+    return b["final_first"] + b["iterate"] * (iters - 2) + b["iterate_last"]
 
 
 def run_ensemble(args, torch, M) -> int:

@@ -251,8 +251,13 @@ int enqueue_step(Engine* e, int step, int count, int iters) {
   for (int l = 2; l <= iters; ++l) {
     const int j = l - 1;
     const ConvCheck chk = j >= 2 ? conv_check(e, rec, j - 1) : none;
+    // A member whose step has not converged by the batch's last iteration
+    // takes the step again from u_0 in the next batch, so of that
+    // iteration's X only X_3 (u_1 = u_0 + X_3) is ever read.
+    StepOut sol = so;
+    sol.stage3_only = l == iters;
     HIP_TRY(launch_iterate(L, cp(xp(j)), pp(xp(l)), e->cfg.sweeps, rec + l, chk,
-                           conv_check(e, rec, j), so, e->q, {}, mi, e->region, f32));
+                           conv_check(e, rec, j), sol, e->q, {}, mi, e->region, f32));
   }
   if (step + 1 < count) return MB4_OK;  // step + 1 takes the final update
   const ConvCheck chk = iters >= 2 ? conv_check(e, rec, iters - 1) : none;

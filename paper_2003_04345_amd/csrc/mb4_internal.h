@@ -167,6 +167,10 @@ hipError_t launch_update_residual(const Lattice& lat, CPlanes3 Uin, Planes3 Uout
 struct StepOut {
   double2* next;
   double2* home;
+  // launch_iterate writes only X_3 of X^{iter+1}: the caller takes the step
+  // again from u_0 if iteration iter + 1 does not converge, so X_1 and X_2
+  // of that iterate are never read.
+  bool stage3_only = false;
 };
 
 // The final update of the previous step, fused into the first solve of the

@@ -1068,7 +1068,8 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const double2 d = t_apply(m, r);
-        Xout.s[m][tsite[j]] = make_double2(xt[j][m].x + d.x, xt[j][m].y + d.y);
+        if (!so.stage3_only || m == 2)
+          Xout.s[m][tsite[j]] = make_double2(xt[j][m].x + d.x, xt[j][m].y + d.y);
         rm.add(d.x);
         rm.add(d.y);
       }

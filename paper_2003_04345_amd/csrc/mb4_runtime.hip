@@ -81,13 +81,14 @@ enum KernelClass {
   kIterateFirst = 6,
   kIterate = 7,
   kFinalFirst = 8,  // final update of a step fused with the next first solve
-  kFinalEnd = 9,    // recorded as such, counted as kFinalUpdate
+  kIterateLast = 9,  // the batch's last iteration: writes only X_3 (see below)
+  kFinalEnd = 10,   // recorded as such, counted as kFinalUpdate
 };
-constexpr int kKernelClasses = 9;
+constexpr int kKernelClasses = 10;
 const char* const kKernelNames[kKernelClasses] = {
     "stage_solve_first", "stage_solve", "stage_sweep", "update_residual_first",
     "update_residual",   "final_update", "iterate_first", "iterate",
-    "final_first"};
+    "final_first",       "iterate_last"};
 
 }  // namespace
 
@@ -315,10 +316,10 @@ int prof_collect(mb4_state* s, const std::vector<int>& m) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
     int cls = r.cls;
-    if (cls == kUpdateResidual || cls == kIterate) {
+    if (cls == kUpdateResidual || cls == kIterate || cls == kIterateLast) {
       if (r.iter == mk)
         cls = kFinalUpdate;
-      else if (r.iter == 1)
+      else if (cls != kIterateLast && r.iter == 1)
         cls = cls == kUpdateResidual ? kUpdateResidualFirst : kIterateFirst;
     } else if (cls == kFinalEnd) {
       if (r.iter != mk) continue;  // returned at once
@@ -445,11 +446,11 @@ double2* batch_u0(mb4_state* s, int k) { return (k & 1) ? s->u0b : s->u0; }
 int enqueue_iterations_fused(mb4_state* s, int step, int count, unsigned long long* rec,
                              int first, int last, int sigma = 0,
                              const unsigned long long* prev_rec = nullptr,
-                             bool emit_final = true) {
+                             bool emit_final = true, bool last_is_final = false) {
   Lattice L = lattice_of(s);
   double2* const src = batch_u0(s, step);
   L.u0 = src;
-  const mb4::StepOut so{step == count - 1 ? s->u0 : batch_u0(s, step + 1), s->u0};
+  mb4::StepOut so{step == count - 1 ? s->u0 : batch_u0(s, step + 1), s->u0};
   const ConvCheck none{nullptr, 0, 0.0, false};
   auto xp = [&](int l) { return x_planes(s, l + sigma); };
   for (int l = first; l <= last; ++l) {
@@ -474,9 +475,14 @@ int enqueue_iterations_fused(mb4_state* s, int step, int count, unsigned long lo
     }
     const int j = l - 1;  // the iteration whose residual this pass forms
     const ConvCheck chk = j >= 2 ? conv_check(s, rec, j - 1) : none;
-    LAUNCH(s, kIterate, step, j,
+    // In a batch, a step that has not converged by its last iteration is
+    // done again from u_0 (step_single), so of that iteration's X only X_3,
+    // which u_1 = u_0 + X_3 takes, is ever read.
+    mb4::StepOut sol = so;
+    sol.stage3_only = last_is_final && l == last;
+    LAUNCH(s, sol.stage3_only ? kIterateLast : kIterate, step, j,
            mb4::launch_iterate(L, cp(xp(j)), pp(xp(l)), s->sweeps, rec + l, chk,
-                               conv_check(s, rec, j), so, s->q, ev_, mb4::Multi{},
+                               conv_check(s, rec, j), sol, s->q, ev_, mb4::Multi{},
                                s->region, s->fp32));
   }
   if (!emit_final) return MB4_OK;
@@ -568,7 +574,8 @@ int enqueue_batch(mb4_state* s, int count, int iters) {
     unsigned long long* rec = s->ring + size_t(k) * s->rec_len;
     const int rc =
         fused ? enqueue_iterations_fused(s, k, count, rec, 1, iters, (k * iters) & 1,
-                                         k > 0 ? rec - s->rec_len : nullptr, k == count - 1)
+                                         k > 0 ? rec - s->rec_len : nullptr, k == count - 1,
+                                         true)
               : enqueue_iterations(s, L, k, rec, 1, iters);
     if (rc != MB4_OK) return rc;
   }
