@@ -166,6 +166,11 @@ def run_ensemble(args, torch, M) -> int:
         tuning = {"region": M.REGION_NAMES[region], "inner_sweeps": sweeps,
                   "ms_per_step": {f"{M.REGION_NAMES[r]}/{sw}": t
                                   for (r, sw), t in sorted(ms.items())}}
+        # The launch form at that shape: one launch per Newton phase, or one
+        # persistent launch per batch (the faster is kept).
+        persistent, form_ms = ens.tune_launch(args.tune_steps)
+        tuning["launch_form"] = "persistent" if persistent else "per-phase"
+        tuning["launch_form_ms_per_step"] = {"per-phase": form_ms[0], "persistent": form_ms[1]}
     if args.warmup:
         if ens.step(args.warmup) != M.MB4_OK:
             raise RuntimeError(f"warmup failed: {M.error_detail()}")

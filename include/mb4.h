@@ -395,6 +395,26 @@ MB4_API int32_t mb4_ensemble_sweeps(const mb4_ensemble* ens);
 MB4_API int mb4_ensemble_tune_all(mb4_ensemble* ens, int32_t steps, int32_t* best_region,
                                   int32_t* best_sweeps, double* ms_per_step);
 
+/* Launch form of the ensemble's batches (Algorithm 1's time loop and
+ * Newton loop for every member).  on = 0 (the default): one launch per
+ * Newton phase for all members, the batch of up to 32 steps replayed from a
+ * captured graph, each step built for a predicted number of iterations.
+ * on != 0: one persistent launch per batch, in which each block owns whole
+ * members and runs every step and every Newton iteration of them itself,
+ * deciding convergence on the device, so that no iteration is predicted and
+ * none is wasted.  Both forms use the same tile kernels and give the same
+ * results bit for bit.  mb4_ensemble_persistent returns the form (-1 for
+ * NULL).  Errors: MB4_EINVAL, MB4_EDEVICE. */
+MB4_API int mb4_ensemble_set_persistent(mb4_ensemble* ens, int32_t on);
+MB4_API int32_t mb4_ensemble_persistent(const mb4_ensemble* ens);
+
+/* Autotuner over the launch form: as mb4_ensemble_tune, timing the
+ * per-phase form and the persistent form at the current region and sweeps
+ * and keeping the faster.  ms_per_step (may be NULL) receives the two times
+ * (per-phase first); *persistent (may be NULL) the form kept (0 or 1). */
+MB4_API int mb4_ensemble_tune_launch(mb4_ensemble* ens, int32_t steps, int32_t* persistent,
+                                     double* ms_per_step);
+
 /* ------------------------------------------------------------------------
  * Serving: solve requests of different lattice sizes and step counts on one
  * GPU with continuous batching.  Requests wait in a FIFO queue and are

@@ -6,10 +6,12 @@ next to this file.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
@@ -28,27 +30,52 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def compile_command(out: str = LIB) -> list[str]:
+# Extra flags of single sources.  mb4_kernels.hip holds the persistent
+# ensemble kernel (k_member_run), whose loops over tiles run whole tile
+# bodies; machine-level loop-invariant code motion hoists their constants
+# and addresses out of those loops, where they stay live and spill (about 30
+# VGPRs, against 8 without it).  The file's per-phase kernels have no such
+# loops and compile to the same instructions either way.
+EXTRA_FLAGS = {"mb4_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
+def common_flags() -> list[str]:
     return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         "-fvisibility=hidden", "-ffp-contract=on",
         # no packed FP32 instructions anywhere in the device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",
         f"-I{INCLUDE}", f"-I{CSRC}",
-        *[os.path.join(CSRC, s) for s in SOURCES],
-        "-o", out,
     ]
+
+
+def compile_commands(out: str, objdir: str) -> list[list[str]]:
+    """One hipcc -c per source (each with its extra flags), then the link."""
+    cmds, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmds.append([hipcc(), *common_flags(), *EXTRA_FLAGS.get(src, []), "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    cmds.append([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out])
+    return cmds
 
 
 def build_library(verbose: bool = False) -> str:
     gen = os.path.join(CSRC, "gen_constants.py")
     subprocess.run([sys.executable, gen], check=True)
     tmp = LIB + ".tmp"
-    cmd = compile_command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    with tempfile.TemporaryDirectory(prefix="mb4_build_") as objdir:
+        cmds = compile_commands(tmp, objdir)
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        workers = max(1, min(len(cmds) - 1, os.cpu_count() or 1, 8))
+        with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+            for f in [pool.submit(subprocess.run, c, check=True) for c in cmds[:-1]]:
+                f.result()
+        subprocess.run(cmds[-1], check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -62,6 +62,12 @@ int energy(Engine* e, double* out);
 // Energy components of one lattice at sites [base, ...) (any member or not).
 int energy_of(Engine* e, const MemberDesc& d, double out[6]);
 
+// One persistent launch per batch (launch_member_run) instead of one launch
+// per Newton phase; the results are the same bit for bit.  Refused when the
+// current region and sweeps have no persistent build.
+int set_persistent(Engine* e, bool on);
+bool persistent(const Engine* e);
+
 int set_region(Engine* e, int region);
 int region(const Engine* e);
 bool region_usable(const Engine* e, int region);

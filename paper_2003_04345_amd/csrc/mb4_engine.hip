@@ -86,6 +86,17 @@ struct Engine {
   int predicted = kInitialPrediction;
   int lower_batches = 0;
 
+  // Persistent form (launch_member_run): workers and their members.
+  bool persistent = false;
+  int cus = 0;
+  int workers = 0;
+  int* d_order = nullptr;   // [max_members]
+  int* d_wfirst = nullptr;  // [wfirst_cap]
+  size_t wfirst_cap = 0;
+  int* d_conv = nullptr;    // [kBatch][max_members]: outcome of each step
+  int* h_conv = nullptr;    // pinned
+  int* d_pred = nullptr;    // [max_members]: each member's predicted iterations
+
   struct GraphEntry {
     int count, iters;
     hipGraphExec_t exec;
@@ -130,8 +141,11 @@ void member_blocks(const Engine* e, const MemberDesc& d, int out[4]) {
   out[kEnergy] = tiles(d.nx, tx) * tiles(d.ny, ty);
 }
 
+int plan_workers(Engine* e);
+
 // Prefix tables of the four launch classes for the current members and
-// region, and a large enough energy scratch.
+// region, a large enough energy scratch and, in the persistent form, the
+// workers' members.
 int upload_blocks(Engine* e) {
   const int n = int(e->desc.size());
   const int stride = e->cfg.max_members + 1;
@@ -182,6 +196,60 @@ int upload_blocks(Engine* e) {
     }
     e->partials_blocks = size_t(e->blocks[kEnergy]);
   }
+  return plan_workers(e);
+}
+
+// Members of each worker of the persistent form: largest first (by tiles of
+// a Newton iteration), each to the worker with the least work so far, and
+// as many workers as fit on the GPU at once (or one per member).
+int plan_workers(Engine* e) {
+  e->workers = 0;
+  const int n = int(e->desc.size());
+  if (!e->persistent || n == 0) return MB4_OK;
+  const int per_cu = member_run_blocks_per_cu(e->cfg.sweeps, e->region, e->cfg.fp32);
+  if (per_cu < 1)
+    return fail(MB4_EINVAL, "no persistent launch for region %s with %d sweeps",
+                region_name(e->region), e->cfg.sweeps);
+  const int w = std::max(1, std::min(n, per_cu * std::max(e->cus, 1)));
+  int ix, iy;
+  iterate_tile(e->region, e->cfg.sweeps, &ix, &iy);
+  std::vector<long long> cost(static_cast<size_t>(n));
+  std::vector<int> by_cost(static_cast<size_t>(n));
+  for (int m = 0; m < n; ++m) {
+    cost[m] = (long long)tiles(e->desc[m].nx, ix) * tiles(e->desc[m].ny, iy);
+    by_cost[m] = m;
+  }
+  std::stable_sort(by_cost.begin(), by_cost.end(),
+                   [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<long long> load(static_cast<size_t>(w), 0);
+  std::vector<std::vector<int>> lists(static_cast<size_t>(w));
+  for (int m : by_cost) {
+    const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+    load[k] += cost[m];
+    lists[k].push_back(m);
+  }
+  std::vector<int> order, wfirst(1, 0);
+  for (const auto& l : lists) {
+    order.insert(order.end(), l.begin(), l.end());
+    wfirst.push_back(int(order.size()));
+  }
+  if (wfirst.size() > e->wfirst_cap) {
+    if (e->d_wfirst != nullptr) {
+      (void)hipFree(e->d_wfirst);
+      e->allocs.erase(std::find(e->allocs.begin(), e->allocs.end(), e->d_wfirst));
+      e->d_wfirst = nullptr;
+      e->wfirst_cap = 0;
+    }
+    const int rc = dalloc(e, reinterpret_cast<void**>(&e->d_wfirst), sizeof(int) * wfirst.size());
+    if (rc != MB4_OK) return rc;
+    e->wfirst_cap = wfirst.size();
+  }
+  HIP_TRY(hipMemcpy(e->d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  const std::vector<int> pred(size_t(n), std::max(1, std::min(e->predicted, e->cfg.max_newton)));
+  HIP_TRY(hipMemcpy(e->d_pred, pred.data(), sizeof(int) * pred.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(e->d_wfirst, wfirst.data(), sizeof(int) * wfirst.size(),
+                    hipMemcpyHostToDevice));
+  e->workers = w;
   return MB4_OK;
 }
 
@@ -267,6 +335,28 @@ int enqueue_step(Engine* e, int step, int count, int iters) {
 }
 
 int enqueue_batch(Engine* e, int count, int iters) {
+  if (e->persistent) {
+    MemberRun run{};
+    run.desc = e->d_desc;
+    run.order = e->d_order;
+    run.wfirst = e->d_wfirst;
+    run.todo = e->d_todo;
+    run.members = int(e->desc.size());
+    run.conv = e->d_conv;
+    run.pred = e->d_pred;
+    run.u0 = e->u0;
+    run.u0b = e->u0b;
+    for (int i = 0; i < 3; ++i) {
+      run.Xa[i] = e->Xa[i];
+      run.Xb[i] = e->Xb[i];
+    }
+    run.eps = e->cfg.eps;
+    run.relative = e->cfg.relative_eps;
+    run.max_newton = e->cfg.max_newton;
+    HIP_TRY(launch_member_run(lattice_of(e), run, e->workers, e->cfg.sweeps, e->region,
+                              e->cfg.fp32, e->q));
+    return MB4_OK;
+  }
   HIP_TRY(launch_clear(e->ring, count * int(e->desc.size()) * e->rec_len, e->q));
   for (int k = 0; k < count; ++k) {
     const int rc = enqueue_step(e, k, count, iters);
@@ -379,6 +469,16 @@ int create(const Config& cfg, Engine** out) {
   if (rc == MB4_OK)
     rc = halloc(e, reinterpret_cast<void**>(&e->h_ring), sizeof(unsigned long long) * words);
   if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->d_energy), sizeof(double) * 6 * mm);
+  if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->d_order), sizeof(int) * mm);
+  if (rc == MB4_OK)
+    rc = dalloc(e, reinterpret_cast<void**>(&e->d_conv), sizeof(int) * size_t(kBatch) * mm);
+  if (rc == MB4_OK) rc = dalloc(e, reinterpret_cast<void**>(&e->d_pred), sizeof(int) * mm);
+  if (rc == MB4_OK)
+    rc = halloc(e, reinterpret_cast<void**>(&e->h_conv), sizeof(int) * size_t(kBatch) * mm);
+  if (rc == MB4_OK) {
+    err = hipDeviceGetAttribute(&e->cus, hipDeviceAttributeMultiprocessorCount, e->device);
+    if (err != hipSuccess) rc = fail(MB4_EDEVICE, "CU count: %s", hipGetErrorString(err));
+  }
   if (rc == MB4_OK) {
     err = hipMemset(e->u0, 0, field);
     if (err == hipSuccess) err = hipMemset(e->V, 0, sizeof(double) * cfg.capacity);
@@ -464,6 +564,37 @@ int run_batch(Engine* e, std::vector<int64_t>& remaining, std::vector<int>& last
   HIP_TRY(hipMemcpyAsync(e->d_todo, e->h_todo, sizeof(int) * members, hipMemcpyHostToDevice,
                          e->cfg.stream));
   hipGraphExec_t exec = nullptr;
+  if (e->persistent) {
+    // One launch for the batch (its graph is keyed by the step count alone).
+    if (e->use_graphs && batch_graph(e, count, 0, &exec) != MB4_OK) {
+      (void)hipGetLastError();
+      e->use_graphs = false;
+      exec = nullptr;
+    }
+    if (exec != nullptr) {
+      HIP_TRY(hipGraphLaunch(exec, e->cfg.stream));
+    } else {
+      const int rc = enqueue_batch(e, count, 0);
+      if (rc != MB4_OK) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(e->h_conv, e->d_conv, sizeof(int) * size_t(count) * members,
+                           hipMemcpyDeviceToHost, e->cfg.stream));
+    HIP_TRY(hipStreamSynchronize(e->cfg.stream));
+    if (nonfinite) nonfinite->assign(size_t(members), 0);
+    for (int m = 0; m < members; ++m) {
+      for (int k = 0; k < e->h_todo[m]; ++k) {
+        const int c = e->h_conv[size_t(k) * members + m];
+        if (c <= 0) {
+          hard_failed.push_back(m);
+          if (nonfinite && c < 0) (*nonfinite)[m] = 1;
+          break;
+        }
+        last_iters[m] = c;
+        --remaining[m];
+      }
+    }
+    return MB4_OK;
+  }
   if (e->use_graphs && batch_graph(e, count, iters, &exec) != MB4_OK) {
     (void)hipGetLastError();
     e->use_graphs = false;
@@ -574,6 +705,23 @@ int set_region(Engine* e, int r) {
   drop_graphs(e);
   return MB4_OK;
 }
+
+int set_persistent(Engine* e, bool on) {
+  if (on == e->persistent) return MB4_OK;
+  HIP_TRY(hipSetDevice(e->device));
+  HIP_TRY(hipStreamSynchronize(e->cfg.stream));
+  e->persistent = on;
+  const int rc = plan_workers(e);
+  if (rc != MB4_OK) {
+    e->persistent = !on;
+    (void)plan_workers(e);
+    return rc;
+  }
+  drop_graphs(e);
+  return MB4_OK;
+}
+
+bool persistent(const Engine* e) { return e->persistent; }
 
 int region(const Engine* e) { return e->region; }
 

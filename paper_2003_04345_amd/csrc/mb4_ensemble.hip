@@ -62,6 +62,7 @@ size_t footprint_bytes(size_t total, int count, int max_newton) {
 struct Shape {
   int region = mb4::kRegion32x32;
   int sweeps = 3;
+  bool persistent = false;  // one launch per batch (mb4_ensemble_set_persistent)
 };
 
 // Times `steps` steps of the ensemble under each shape (one untimed pass
@@ -80,7 +81,7 @@ int tune_shapes(mb4_ensemble* e, int32_t steps, const std::vector<Shape>& shapes
   if (err != hipSuccess) return fail(MB4_ENOMEM, "tune backup: %s", hipGetErrorString(err));
   const std::vector<int64_t> done0 = e->steps_done;
   const std::vector<int> iters0 = e->last_iters;
-  const Shape shape0{eng::region(g), eng::sweeps(g)};
+  const Shape shape0{eng::region(g), eng::sweeps(g), eng::persistent(g)};
   const int pred0 = eng::iteration_prediction(g);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   times->assign(shapes.size(), -1.0);
@@ -102,6 +103,7 @@ int tune_shapes(mb4_ensemble* e, int32_t steps, const std::vector<Shape>& shapes
       rc = eng::set_region(g, sh.region);
       if (rc == MB4_OK) rc = eng::set_sweeps(g, sh.sweeps);
     }
+    if (rc == MB4_OK) rc = eng::set_persistent(g, sh.persistent);
     return rc;
   };
   int rc = eng::save_u0(g, backup);
@@ -350,8 +352,9 @@ int mb4_ensemble_tune(mb4_ensemble* e, int32_t steps, int32_t* best, double* ms_
   if (rc != MB4_OK) return rc;
   if (steps < 1) return fail(MB4_EINVAL, "steps must be >= 1");
   const int sw = eng::sweeps(e->engine);
+  const bool pe = eng::persistent(e->engine);
   std::vector<Shape> shapes;
-  for (int r = 0; r < mb4::kRegionCount; ++r) shapes.push_back(Shape{r, sw});
+  for (int r = 0; r < mb4::kRegionCount; ++r) shapes.push_back(Shape{r, sw, pe});
   std::vector<double> times;
   Shape chosen{};
   rc = tune_shapes(e, steps, shapes, &times, &chosen);
@@ -367,15 +370,43 @@ int mb4_ensemble_tune_all(mb4_ensemble* e, int32_t steps, int32_t* best_region,
   int rc = check(e);
   if (rc != MB4_OK) return rc;
   if (steps < 1) return fail(MB4_EINVAL, "steps must be >= 1");
+  const bool pe = eng::persistent(e->engine);
   std::vector<Shape> shapes;
   for (int sw = 1; sw <= mb4::kMaxFusedSweeps; ++sw)
-    for (int r = 0; r < mb4::kRegionCount; ++r) shapes.push_back(Shape{r, sw});
+    for (int r = 0; r < mb4::kRegionCount; ++r) shapes.push_back(Shape{r, sw, pe});
   std::vector<double> times;
   Shape chosen{};
   rc = tune_shapes(e, steps, shapes, &times, &chosen, /*min_sweeps=*/2);
   if (rc != MB4_OK) return rc;
   if (best_region) *best_region = chosen.region;
   if (best_sweeps) *best_sweeps = chosen.sweeps;
+  if (ms_per_step)
+    for (size_t k = 0; k < times.size(); ++k) ms_per_step[k] = times[k];
+  return MB4_OK;
+}
+
+int mb4_ensemble_set_persistent(mb4_ensemble* e, int32_t on) {
+  const int rc = check(e);
+  if (rc != MB4_OK) return rc;
+  return eng::set_persistent(e->engine, on != 0);
+}
+
+int32_t mb4_ensemble_persistent(const mb4_ensemble* e) {
+  return e == nullptr ? -1 : (eng::persistent(e->engine) ? 1 : 0);
+}
+
+int mb4_ensemble_tune_launch(mb4_ensemble* e, int32_t steps, int32_t* persistent,
+                             double* ms_per_step) {
+  int rc = check(e);
+  if (rc != MB4_OK) return rc;
+  if (steps < 1) return fail(MB4_EINVAL, "steps must be >= 1");
+  const int r = eng::region(e->engine), sw = eng::sweeps(e->engine);
+  const std::vector<Shape> shapes{Shape{r, sw, false}, Shape{r, sw, true}};
+  std::vector<double> times;
+  Shape chosen{};
+  rc = tune_shapes(e, steps, shapes, &times, &chosen);
+  if (rc != MB4_OK) return rc;
+  if (persistent) *persistent = chosen.persistent ? 1 : 0;
   if (ms_per_step)
     for (size_t k = 0; k < times.size(); ++k) ms_per_step[k] = times[k];
   return MB4_OK;

@@ -222,6 +222,51 @@ hipError_t launch_final_update(const Lattice& lat, CPlanes3 X, ConvCheck check, 
                                StepOut so, hipStream_t stream, LaunchEvents ev = {},
                                const Multi& mu = {});
 
+// ---------------------------------------------------------------------------
+// A batch of the multi-lattice engine as one persistent launch.  Each block
+// is a worker that owns whole members, order[wfirst[w] .. wfirst[w + 1]),
+// and takes each of them through its todo[m] steps one after the other,
+// every Newton iteration of a step included (Algorithm 1's loop runs on the
+// device, up to max_newton iterations, with the stopping test of ConvCheck).
+// A member's tiles are only ever touched by its own block, so the block's
+// barriers order one phase (a Newton iteration over all tiles) before the
+// next, and no grid-wide synchronisation exists.  Step k of a member reads
+// u_0 from u0 (k even) or u0b (k odd) and sends u_1 on through the fused
+// first solve of step k + 1, the last step's u_1 going to u0 (home); X^l
+// alternates between Xa and Xb.  conv[k * members + m] receives the
+// outcome of step k: the iteration it converged at (>= 1), 0 if it had not
+// converged after max_newton iterations, -1 if an update was not finite.
+// A member stops at such a failed step and keeps its u_0 in u0.  pred[m] is
+// the member's predicted iteration count, carried from batch to batch: that
+// iteration writes only X_3 of its iterate, and a step that needs more is
+// taken again from its u_0 with one more (as the per-phase form does in its
+// next batch), so the results do not depend on the prediction.
+struct MemberRun {
+  const MemberDesc* desc;  // device [members]
+  const int* order;        // device: members, worker after worker
+  const int* wfirst;       // device [workers + 1]
+  const int* todo;         // device [members]: steps of the batch
+  int members;
+  int* conv;               // device [steps][members]
+  int* pred;               // device [members]
+  double2* u0;
+  double2* u0b;
+  double2* Xa[3];
+  double2* Xb[3];
+  double eps;
+  bool relative;
+  int max_newton;
+};
+
+// lat carries the ensemble-wide V (and per-site g, if any); `workers`
+// blocks.  Region and sweeps as for launch_iterate.
+hipError_t launch_member_run(const Lattice& lat, const MemberRun& run, int workers, int sweeps,
+                             int region, bool fp32, hipStream_t stream, LaunchEvents ev = {});
+
+// Blocks of launch_member_run that are resident on one CU at a time (0 if
+// the shape is not built).
+int member_run_blocks_per_cu(int sweeps, int region, bool fp32);
+
 // (p, q) arrays <-> interleaved double2 field of n sites.
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,
                              hipStream_t stream);

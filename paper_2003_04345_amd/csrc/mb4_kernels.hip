@@ -192,6 +192,15 @@ __device__ __forceinline__ T* offset_ptr(T* p, long long n) {
   return p == nullptr ? p : p + n;
 }
 
+// threadIdx.x through an empty asm statement, so that the compiler cannot
+// hoist what a tile body derives from it out of a loop over tiles
+// (k_member_run), where it would stay live, and spill, across the loop.
+__device__ __forceinline__ int thread_index() {
+  int t = static_cast<int>(threadIdx.x);
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Block-wide max of v posted to *slot.  Device-scope atomics on one address
 // serialise across the XCDs; most blocks hold a value below the running
 // maximum, so thread 0 reads it first (a coherent load) and only posts a
@@ -576,39 +585,26 @@ __device__ __forceinline__ double2* step_dst(const StepOut& so, const Multi& mu,
 // unrolling.
 constexpr int region_threads(int rx, int ry) { return rx == 32 && ry == 16 ? rx * ry : rx * ry / 2; }
 
+// The work of one block of k_stage_solve on tile b of the lattice L (whose
+// pointers, like every pointer here, are already moved to the block's
+// member), in the LDS planes sr.  pmode (PREV): how this step's u_0 is
+// formed (PrevStep): 0 as it is, 1 the previous step's u_0 + X_3, 2 the
+// previous step's u_0 (it did not converge).  final_only (PREV): the member
+// took its last step of the batch, and the tile gets only that step's final
+// update.
 template <int RX, int RY, int H, int MODE, class RT>
-__global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(
-    Lattice L, CPlanes3 phib_in, Planes3 phib_out, Planes3 out, unsigned long long* rslot,
-    ConvCheck chk, FirstArgs fa, Multi mu, PrevStep pv) {
+__device__ __forceinline__ void stage_solve_tile(const Lattice& L, CPlanes3 phib_in,
+                                                 Planes3 phib_out, Planes3 out,
+                                                 unsigned long long* rslot, FirstArgs fa,
+                                                 const PrevStep& pv, int pmode, bool final_only,
+                                                 int b, vec2_t<RT> (*sr)[RX * RY]) {
   constexpr bool FIRST = MODE != kSolvePlain;
   constexpr bool XOUT = MODE == kSolveFirstX || MODE == kSolveFirstXPrev;
   constexpr bool PREV = MODE == kSolveFirstXPrev;
   static_assert(XOUT || sizeof(RT) == sizeof(double), "FP32 solves exist on the fused path only");
   using R2 = vec2_t<RT>;
   constexpr int kSolveThreads = region_threads(RX, RY);
-  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
-  // PREV: how this step's u_0 is formed (PrevStep): 0 as it is, 1 the
-  // previous step's u_0 + X_3, 2 the previous step's u_0 (it did not
-  // converge).
-  int pmode = 0;
-  if (PREV) {
-    if (mu.todo != nullptr && mu.step - 1 >= mu.todo[w.m]) return;
-    offset_check(pv.chk, w.rec);
-    offset_check(pv.fin, w.rec);
-    pmode = converged_at(pv.chk) ? 0 : (converged_at(pv.fin) ? 1 : 2);
-    pv.u0 = offset_ptr(pv.u0, w.base);
-    offset_planes(pv.X, w.base);
-    pv.next = offset_ptr(pv.next, w.base);
-    pv.home = offset_ptr(pv.home, w.base);
-  }
-  if (w.skip && pmode == 0) return;
-  offset_check(chk, w.rec);
-  if (converged_at(chk)) return;
-  offset_planes(phib_in, w.base);
-  offset_planes(phib_out, w.base);
-  offset_planes(out, w.base);
-  rslot = offset_ptr(rslot, w.rec);
-  fa.u0max_slot = offset_ptr(fa.u0max_slot, w.rec);
+  const int tid = thread_index();
   constexpr int RN = RX * RY;
   constexpr int TSX = RX - 2 * H, TSY = RY - 2 * H;
   constexpr int PER = RN / kSolveThreads;
@@ -616,12 +612,12 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   constexpr int UX = RX + 2, UN = FIRST ? UX * (RY + 2) : 1;
   // u_0 on the region plus a one-site ring (FIRST) shares the LDS of the
   // stage iterates: it is dead once the right-hand sides are formed.
-  __shared__ R2 sr[3][RN];
-  static_assert(UN * sizeof(double2) <= sizeof(sr), "u_0 staging must fit the iterate buffer");
+  static_assert(UN * sizeof(double2) <= 3 * RN * sizeof(R2),
+                "u_0 staging must fit the iterate buffer");
   double2* const su = reinterpret_cast<double2*>(&sr[0][0]);
   const int nx = L.nx, ny = L.ny;
   int tx0, ty0;
-  strip_tile(w.b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
+  strip_tile(b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
   tx0 *= TSX;
   ty0 *= TSY;
   const bool fast = nx >= RX + 2 && ny >= RY + 2;
@@ -635,12 +631,11 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
     }
     return u;
   };
-  if (PREV && w.skip) {
-    // The member took its last step of the batch: only its final update.
+  if (PREV && final_only) {
     if (pmode == 2 && pv.home == pv.u0) return;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int idx = threadIdx.x + j * kSolveThreads;
+      const int idx = tid + j * kSolveThreads;
       const int lx = idx % RX, ly = idx / RX;
       if (lx >= H && lx < H + TSX && ly >= H && ly < H + TSY && tx0 + lx - H < nx &&
           ty0 + ly - H < ny) {
@@ -657,7 +652,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   double vv[PER], gg[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kSolveThreads;
+    const int idx = tid + j * kSolveThreads;
     const int lx = idx % RX, ly = idx / RX;
     gsite[j] = wrap_in(ty0 - H + ly, ny, fast) * nx + wrap_in(tx0 - H + lx, nx, fast);
     vv[j] = L.V[gsite[j]];
@@ -670,7 +665,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
     double2 st[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const int e = threadIdx.x + k * kSolveThreads;
+      const int e = tid + k * kSolveThreads;
       if (e < UN) {
         const int ex = e % UX, ey = e / UX;
         const int site =
@@ -680,7 +675,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
     }
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const int e = threadIdx.x + k * kSolveThreads;
+      const int e = tid + k * kSolveThreads;
       if (e < UN) su[e] = st[k];
     }
     __syncthreads();
@@ -692,7 +687,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   NormAcc um;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kSolveThreads;
+    const int idx = tid + j * kSolveThreads;
     const int lx = idx % RX, ly = idx / RX;
     const int site = gsite[j];
     const int e = (ly + 1) * UX + lx + 1;
@@ -726,7 +721,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   // First sweep (from r = 0): the local 2x2 solves.
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kSolveThreads;
+    const int idx = tid + j * kSolveThreads;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const RT hl = RT(L.h * MB4_LAMBDA[i]);
@@ -750,14 +745,14 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
         const int ip = i == 0 ? 2 : i - 1;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-          const int idx = threadIdx.x + j * kSolveThreads;
+          const int idx = tid + j * kSolveThreads;
           const int lx = idx % RX, ly = idx / RX;
           if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) sr[ip][idx] = rn[j];
         }
       }
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
-        const int idx = threadIdx.x + j * kSolveThreads;
+        const int idx = tid + j * kSolveThreads;
         const int lx = idx % RX, ly = idx / RX;
         if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
           const R2 r1 = sr[i][idx - 1], r2 = sr[i][idx + 1];
@@ -774,7 +769,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int idx = threadIdx.x + j * kSolveThreads;
+      const int idx = tid + j * kSolveThreads;
       const int lx = idx % RX, ly = idx / RX;
       if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) sr[2][idx] = rn[j];
     }
@@ -785,7 +780,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   NormAcc rm;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kSolveThreads;
+    const int idx = tid + j * kSolveThreads;
     const int lx = idx % RX, ly = idx / RX;
     if (lx >= H && lx < H + TSX && ly >= H && ly < H + TSY && tx0 + lx - H < nx &&
         ty0 + ly - H < ny) {
@@ -812,6 +807,36 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
   if (FIRST && fa.u0max_slot != nullptr) block_max_to<kSolveThreads>(um.bits(), fa.u0max_slot);
 }
 
+template <int RX, int RY, int H, int MODE, class RT>
+__global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) void k_stage_solve(
+    Lattice L, CPlanes3 phib_in, Planes3 phib_out, Planes3 out, unsigned long long* rslot,
+    ConvCheck chk, FirstArgs fa, Multi mu, PrevStep pv) {
+  constexpr bool PREV = MODE == kSolveFirstXPrev;
+  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
+  int pmode = 0;
+  if (PREV) {
+    if (mu.todo != nullptr && mu.step - 1 >= mu.todo[w.m]) return;
+    offset_check(pv.chk, w.rec);
+    offset_check(pv.fin, w.rec);
+    pmode = converged_at(pv.chk) ? 0 : (converged_at(pv.fin) ? 1 : 2);
+    pv.u0 = offset_ptr(pv.u0, w.base);
+    offset_planes(pv.X, w.base);
+    pv.next = offset_ptr(pv.next, w.base);
+    pv.home = offset_ptr(pv.home, w.base);
+  }
+  if (w.skip && pmode == 0) return;
+  offset_check(chk, w.rec);
+  if (converged_at(chk)) return;
+  offset_planes(phib_in, w.base);
+  offset_planes(phib_out, w.base);
+  offset_planes(out, w.base);
+  rslot = offset_ptr(rslot, w.rec);
+  fa.u0max_slot = offset_ptr(fa.u0max_slot, w.rec);
+  __shared__ vec2_t<RT> sr[3][RX * RY];
+  stage_solve_tile<RX, RY, H, MODE, RT>(L, phib_in, phib_out, out, rslot, fa, pv, pmode,
+                                        PREV && w.skip, w.b, sr);
+}
+
 // ---------------------------------------------------------------------------
 // One Newton iteration's residual fused with the next iteration's stage solve,
 // so that Phibar never goes through HBM.  The iterate is held as X^iter =
@@ -830,29 +855,40 @@ __global__ __launch_bounds__(region_threads(RX, RY), sizeof(RT) == 4 ? 6 : 4) vo
 // residual on the region less one ring, the sweeps on shrinking rings, and
 // the (RX - 2 - 2H) x (RY - 2 - 2H) tile in the middle is written back.  As
 // in k_stage_solve, each region position computes the values of its (wrapped)
-// lattice site from region neighbours only.
+// lattice site from region neighbours only.  iterate_tile_body is the work of
+// one block; k_iterate and k_member_run run it.
+
+// X^iter of the tile is kept in LDS too when the stage planes and it fit
+// this block's share of the CU's 160 KiB at the occupancy of the launch
+// bounds (4 waves per SIMD); otherwise it is read again at the end.  Holding
+// it in registers through the sweeps would spill.  iterate_park() is the
+// number of its sites so kept (1 when it is read again).
+constexpr int iterate_park(int rx, int ry, int h) {
+  return (rx * ry * 48 + (rx - 2 - 2 * h) * (ry - 2 - 2 * h) * 48 + 64 <=
+          160 * 1024 * (region_threads(rx, ry) / 64) / (4 * 4))
+             ? (rx - 2 - 2 * h) * (ry - 2 - 2 * h)
+             : 1;
+}
+
+// The work of one block of k_iterate on tile b of L (pointers moved to the
+// block's member) in the LDS planes sb and the X park sx.  at: iteration
+// iter - 1 already met the tolerance, and the tile gets u_1 = u_0 + X_3,
+// written to dst.  stage3_only: of X^{iter+1} only X_3 is written.
 template <int RX, int RY, int H, class RT>
-__global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L, CPlanes3 Xin, Planes3 Xout,
-                                                          unsigned long long* rnext,
-                                                          ConvCheck chk, ConvCheck fin,
-                                                          StepOut so, Multi mu) {
+__device__ __forceinline__ void iterate_tile_body(const Lattice& L, CPlanes3 Xin, Planes3 Xout,
+                                                  unsigned long long* rnext, bool at,
+                                                  double2* dst, bool stage3_only, int b,
+                                                  double2 (*sb)[RX * RY],
+                                                  double2 (*sx)[iterate_park(RX, RY, H)]) {
   using R2 = vec2_t<RT>;
   constexpr int kIterThreads = region_threads(RX, RY);
-  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
-  if (w.skip) return;
-  offset_check(chk, w.rec);
-  offset_check(fin, w.rec);
-  rnext = offset_ptr(rnext, w.rec);
-  if (converged_at(chk)) return;
-  const bool at = converged_at(fin);
-  offset_planes(Xin, w.base);
-  offset_planes(Xout, w.base);
+  const int tid = thread_index();
   constexpr int RN = RX * RY;
   constexpr int TSX = RX - 2 - 2 * H, TSY = RY - 2 - 2 * H;
   constexpr int PER = RN / kIterThreads;
   const int nx = L.nx, ny = L.ny;
   int tx0, ty0;
-  strip_tile(w.b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
+  strip_tile(b, (nx + TSX - 1) / TSX, (ny + TSY - 1) / TSY, tx0, ty0);
   tx0 *= TSX;
   ty0 *= TSY;
   const int ox = tx0 - H - 1, oy = ty0 - H - 1;  // region origin
@@ -860,10 +896,9 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
 
   if (at) {
     // Final update on this block's tile only.
-    double2* const dst = offset_ptr(step_dst(so, mu, w.m), w.base);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int idx = threadIdx.x + j * kIterThreads;
+      const int idx = tid + j * kIterThreads;
       const int lx = idx % RX, ly = idx / RX;
       if (lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY &&
           ox + lx < nx && oy + ly < ny) {
@@ -875,16 +910,9 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
     return;
   }
 
-  // W_i (FP64), then the stage iterates (RT) in the same LDS.  X^iter of
-  // the tile is kept in LDS too when both fit this block's share of the
-  // CU's 160 KiB at the occupancy of the launch bounds (4 waves per SIMD);
-  // otherwise it is read again at the end.  Holding it in registers through
-  // the sweeps would spill.
-  constexpr int TN = TSX * TSY;
-  constexpr int kLdsShare = 160 * 1024 * (kIterThreads / 64) / (4 * 4);
-  constexpr bool XLDS = RN * 48 + TN * 48 + 64 <= kLdsShare;
-  __shared__ double2 sb[3][RN];
-  __shared__ double2 sx[3][XLDS ? TN : 1];
+  // W_i (FP64), then the stage iterates (RT) in the same LDS, and X^iter
+  // of the tile parked in sx (iterate_park).
+  constexpr bool XLDS = iterate_park(RX, RY, H) > 1;
   R2(*const si)[RN] = reinterpret_cast<R2(*)[RN]>(&sb[0][0]);
   int gsite[PER];
   double2 u0v[PER];
@@ -894,7 +922,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   // issued before the first LDS store, so that their latencies overlap.
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kIterThreads;
+    const int idx = tid + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
     const int site = wrap_in(oy + ly, ny, fast) * nx + wrap_in(ox + lx, nx, fast);
     gsite[j] = site;
@@ -906,7 +934,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   }
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kIterThreads;
+    const int idx = tid + j * kIterThreads;
     if (XLDS) {
       const int tx = idx % RX - (H + 1), ty = idx / RX - (H + 1);
       if (tx >= 0 && tx < TSX && ty >= 0 && ty < TSY) {
@@ -930,7 +958,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   RT inv[PER][3];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kIterThreads;
+    const int idx = tid + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
     blk[j] = block_in<RT>(site_block(L, u0v[j], vv[j], gg[j]));
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
@@ -981,7 +1009,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   // its values need no registers across the barrier.
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kIterThreads;
+    const int idx = tid + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
     if (lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
 #pragma unroll
@@ -1005,14 +1033,14 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
         const int ip = i == 0 ? 2 : i - 1;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-          const int idx = threadIdx.x + j * kIterThreads;
+          const int idx = tid + j * kIterThreads;
           const int lx = idx % RX, ly = idx / RX;
           if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) si[ip][idx] = rn[j];
         }
       }
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
-        const int idx = threadIdx.x + j * kIterThreads;
+        const int idx = tid + j * kIterThreads;
         const int lx = idx % RX, ly = idx / RX;
         if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) {
           const R2 q1 = si[i][idx - 1], q2 = si[i][idx + 1];
@@ -1031,7 +1059,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   double2 xt[PER][3];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kIterThreads;
+    const int idx = tid + j * kIterThreads;
     const int lx = idx % RX, ly = idx / RX;
     const bool tile = lx >= H + 1 && lx < H + 1 + TSX && ly >= H + 1 && ly < H + 1 + TSY &&
                       ox + lx < nx && oy + ly < ny;
@@ -1045,7 +1073,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int idx = threadIdx.x + j * kIterThreads;
+      const int idx = tid + j * kIterThreads;
       const int lx = idx % RX, ly = idx / RX;
       if (lx >= 2 && lx <= RX - 3 && ly >= 2 && ly <= RY - 3) si[2][idx] = rn[j];
     }
@@ -1055,7 +1083,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
   NormAcc rm;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int idx = threadIdx.x + j * kIterThreads;
+    const int idx = tid + j * kIterThreads;
     if (tsite[j] >= 0) {
       if (XLDS) {
         const int tp = (idx / RX - (H + 1)) * TSX + (idx % RX - (H + 1));
@@ -1068,7 +1096,7 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const double2 d = t_apply(m, r);
-        if (!so.stage3_only || m == 2)
+        if (!stage3_only || m == 2)
           Xout.s[m][tsite[j]] = make_double2(xt[j][m].x + d.x, xt[j][m].y + d.y);
         rm.add(d.x);
         rm.add(d.y);
@@ -1076,6 +1104,26 @@ __global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L
     }
   }
   block_max_to<kIterThreads>(rm.bits(), rnext);
+}
+
+template <int RX, int RY, int H, class RT>
+__global__ __launch_bounds__(region_threads(RX, RY), 4) void k_iterate(Lattice L, CPlanes3 Xin, Planes3 Xout,
+                                                          unsigned long long* rnext,
+                                                          ConvCheck chk, ConvCheck fin,
+                                                          StepOut so, Multi mu) {
+  const Loc w = locate(mu, L, xcd_block(blockIdx.x, gridDim.x));
+  if (w.skip) return;
+  offset_check(chk, w.rec);
+  offset_check(fin, w.rec);
+  rnext = offset_ptr(rnext, w.rec);
+  if (converged_at(chk)) return;
+  const bool at = converged_at(fin);
+  offset_planes(Xin, w.base);
+  offset_planes(Xout, w.base);
+  double2* const dst = at ? offset_ptr(step_dst(so, mu, w.m), w.base) : nullptr;
+  __shared__ double2 sb[3][RX * RY];
+  __shared__ double2 sx[3][iterate_park(RX, RY, H)];
+  iterate_tile_body<RX, RY, H, RT>(L, Xin, Xout, rnext, at, dst, so.stage3_only, w.b, sb, sx);
 }
 
 // Final update of the last step of a batch, site by site (launch_final_update).
@@ -1101,6 +1149,174 @@ __global__ __launch_bounds__(kFinalSites) void k_final_update(Lattice L, CPlanes
     u.y += x.y;
   }
   dst[site] = u;
+}
+
+// A value every lane of the wave holds, moved to scalar registers.
+__device__ __forceinline__ double uniform_double(double x) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(b)));
+  const long long hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ MemberDesc uniform_desc(const MemberDesc& d) {
+  MemberDesc u;
+  u.nx = __builtin_amdgcn_readfirstlane(d.nx);
+  u.ny = __builtin_amdgcn_readfirstlane(d.ny);
+  u.t = uniform_double(d.t);
+  u.shift = uniform_double(d.shift);
+  u.g = uniform_double(d.g);
+  u.h = uniform_double(d.h);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(d.base)));
+  const long long hi = __builtin_amdgcn_readfirstlane(static_cast<int>(d.base >> 32));
+  u.base = static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo);
+  return u;
+}
+
+// A batch of the multi-lattice engine in one launch (MemberRun): block w
+// takes its members one after the other through all their steps.  Each
+// Newton iteration of a step is the member's tiles, walked in the order of
+// the per-phase launches, with the same tile bodies and the same LDS layout,
+// so the results are those of the per-phase launches bit for bit.  The
+// update norm of the iteration in progress is reduced into LDS (rec[1];
+// ||u_0||_inf in rec[0]), and thread 0 alone takes the decision, which the
+// block reads after a barrier: every thread follows the same branch.
+template <int RX, int RY, int H, class RT>
+__global__ __launch_bounds__(region_threads(RX, RY), 4) void k_member_run(Lattice base,
+                                                                          MemberRun run) {
+  using R2 = vec2_t<RT>;
+  constexpr int NT = region_threads(RX, RY);
+  constexpr int RN = RX * RY;
+  constexpr int PARK = iterate_park(RX, RY, H);
+  constexpr size_t kSolveBytes = sizeof(R2) * 3 * RN;
+  constexpr size_t kIterBytes = sizeof(double2) * 3 * (RN + PARK);
+  __shared__ __align__(16) unsigned char arena[kSolveBytes > kIterBytes ? kSolveBytes : kIterBytes];
+  __shared__ unsigned long long rec[2];
+  __shared__ int verdict;
+  R2(*const sr)[RN] = reinterpret_cast<R2(*)[RN]>(arena);
+  double2(*const sb)[RN] = reinterpret_cast<double2(*)[RN]>(arena);
+  double2(*const sx)[PARK] = reinterpret_cast<double2(*)[PARK]>(arena + sizeof(double2) * 3 * RN);
+  constexpr int FSX = RX - 2 * H, FSY = RY - 2 * H;          // tile of the first solve
+  constexpr int ISX = RX - 2 - 2 * H, ISY = RY - 2 - 2 * H;  // tile of an iteration
+  const CPlanes3 cnone{{nullptr, nullptr, nullptr}};
+  const Planes3 none{{nullptr, nullptr, nullptr}};
+  // Thread 0's verdict on the iteration just done: 1 converged, 0 not yet,
+  // -1 a norm that is not finite.
+  auto decide = [&]() {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double r = bits_double(rec[1]);
+      const double tol = run.relative ? conv_tol(run.eps, bits_double(rec[0])) : run.eps;
+      verdict = r <= tol ? 1 : (isfinite(r) ? 0 : -1);
+      rec[1] = 0ull;
+    }
+    __syncthreads();
+    return verdict;
+  };
+  for (int k = run.wfirst[blockIdx.x]; k < run.wfirst[blockIdx.x + 1]; ++k) {
+    // The member and its descriptor are the same for the whole block; read
+    // through the first lane, they stay in scalar registers.
+    const int m = __builtin_amdgcn_readfirstlane(run.order[k]);
+    const MemberDesc d = uniform_desc(run.desc[m]);
+    Lattice L = base;
+    L.nx = d.nx;
+    L.ny = d.ny;
+    L.t = d.t;
+    L.shift = d.shift;
+    L.g = d.g;
+    L.h = d.h;
+    L.V += d.base;
+    if (L.gs != nullptr) L.gs += d.base;
+    const int nf = ((d.nx + FSX - 1) / FSX) * ((d.ny + FSY - 1) / FSY);
+    const int ni = ((d.nx + ISX - 1) / ISX) * ((d.ny + ISY - 1) / ISY);
+    double2* const home = run.u0 + d.base;
+    auto u0_of = [&](int step) { return ((step & 1) ? run.u0b : run.u0) + d.base; };
+    auto x_of = [&](int par) {
+      double2* const* a = par ? run.Xa : run.Xb;
+      return Planes3{{a[0] + d.base, a[1] + d.base, a[2] + d.base}};
+    };
+    auto cx_of = [&](int par) {
+      const Planes3 p = x_of(par);
+      return CPlanes3{{p.s[0], p.s[1], p.s[2]}};
+    };
+    int par = 0;  // X^l of the step in progress lives in x_of(par)
+    const int steps = run.todo[m];
+    // Predicted iteration count: its iteration writes only X_3 (as the
+    // per-phase form's last iteration does); a step that needs more is taken
+    // again from its u_0 with one iteration more.  It follows a count up at
+    // once and down after two lower steps.
+    int pred = __builtin_amdgcn_readfirstlane(run.pred[m]), lower = 0;
+    for (int step = 0; step < steps; ++step) {
+      if (threadIdx.x == 0) rec[0] = rec[1] = 0ull;
+      __syncthreads();
+      const FirstArgs fa{run.relative ? &rec[0] : nullptr, false};
+      const ConvCheck nochk{nullptr, 0, 0.0, false};
+      const PrevStep pv{u0_of(step - 1), cx_of(par), nochk, nochk, u0_of(step), home};
+      L.u0 = u0_of(step);
+      // pmode 1: this step's u_0 is formed from the previous step's by the
+      // first solve (and written to u0_of(step)); 0 on the member's first
+      // step of the batch and when a step is taken again.
+      int pmode = step > 0 ? 1 : 0;
+      int it, v;
+      for (;;) {
+        // Newton iteration 1, fused with the previous step's final update.
+        for (int b = 0; b < nf; ++b)
+          stage_solve_tile<RX, RY, H, kSolveFirstXPrev, RT>(L, cnone, none, x_of(par ^ 1),
+                                                            &rec[1], fa, pv, pmode, false, b, sr);
+        par ^= 1;
+        it = 1;
+        v = decide();
+        bool short_of = false;
+        while (v == 0 && it < run.max_newton) {
+          const bool last = it + 1 == pred;
+          for (int b = 0; b < ni; ++b)
+            iterate_tile_body<RX, RY, H, RT>(L, cx_of(par), x_of(par ^ 1), &rec[1], false,
+                                             nullptr, last, b, sb, sx);
+          par ^= 1;
+          ++it;
+          v = decide();
+          if (v == 0 && last && it < run.max_newton) {
+            short_of = true;
+            break;
+          }
+        }
+        if (!short_of) break;
+        pred = it + 1;
+        lower = 0;
+        pmode = 0;
+      }
+      if (v == 1) {
+        if (it >= pred) {
+          pred = it;
+          lower = 0;
+        } else if (++lower >= 2) {
+          pred = it;
+          lower = 0;
+        }
+      }
+      if (threadIdx.x == 0) run.conv[step * run.members + m] = v == 1 ? it : (v < 0 ? -1 : 0);
+      if (v != 1) {
+        // The step failed for good: the member keeps this step's u_0.
+        if (step & 1) {
+          const double2* const src = u0_of(step);
+          for (int i = threadIdx.x; i < d.nx * d.ny; i += NT) home[i] = src[i];
+        }
+        break;
+      }
+      if (step == steps - 1) {
+        // u_1 = u_0 + X_3 of the converged iterate, into the home buffer,
+        // site by site (home may be this step's u_0).
+        const double2* const u = L.u0;
+        const double2* const x3 = x_of(par).s[2];
+        for (int i = thread_index(); i < d.nx * d.ny; i += NT) {
+          const double2 a = u[i], x = x3[i];
+          home[i] = make_double2(a.x + x.x, a.y + x.y);
+        }
+      }
+    }
+    if (threadIdx.x == 0) run.pred[m] = pred;
+    __syncthreads();
+  }
 }
 
 // One more block-Jacobi sweep from the iterate rin (solves with more than
@@ -1550,6 +1766,75 @@ hipError_t launch_final_update(const Lattice& lat, CPlanes3 X, ConvCheck check, 
   const dim3 grid(mu.desc != nullptr ? mu.blocks : (n + kFinalSites - 1) / kFinalSites),
       block(kFinalSites);
   MB4_LAUNCH(k_final_update, grid, block, ev, lat, X, check, fin, so, n, mu);
+}
+
+namespace {
+
+template <int RX, int RY, class RT>
+const void* member_run_kernel(int sweeps) {
+  switch (sweeps) {
+    case 1:
+      return reinterpret_cast<const void*>(&k_member_run<RX, RY, 0, RT>);
+    case 2:
+      return reinterpret_cast<const void*>(&k_member_run<RX, RY, 1, RT>);
+    case 3:
+      return reinterpret_cast<const void*>(&k_member_run<RX, RY, 2, RT>);
+    case 4:
+      return reinterpret_cast<const void*>(&k_member_run<RX, RY, 3, RT>);
+    default:
+      return nullptr;
+  }
+}
+
+const void* member_run_kernel(int sweeps, int region, bool fp32) {
+  if (fp32) return region == kRegion32x32 ? member_run_kernel<32, 32, float>(sweeps) : nullptr;
+  switch (region) {
+    case kRegion32x32:
+      return member_run_kernel<32, 32, double>(sweeps);
+    case kRegion64x16:
+      return member_run_kernel<64, 16, double>(sweeps);
+    case kRegion32x16:
+      return member_run_kernel<32, 16, double>(sweeps);
+    default:
+      return nullptr;
+  }
+}
+
+int member_run_threads(int region) {
+  return region_threads(region_x(region), region_y(region));
+}
+
+}  // namespace
+
+hipError_t launch_member_run(const Lattice& lat, const MemberRun& run, int workers, int sweeps,
+                             int region, bool fp32, hipStream_t stream, LaunchEvents ev) {
+  const void* fn = member_run_kernel(sweeps, region, fp32);
+  if (fn == nullptr || workers < 1) return hipErrorInvalidValue;
+  Lattice l = lat;
+  MemberRun r = run;
+  void* args[] = {&l, &r};
+  const dim3 grid(workers), block(member_run_threads(region));
+  if (ev.start == nullptr && ev.stop == nullptr) {
+    const hipError_t err = hipLaunchKernel(fn, grid, block, args, 0, stream);
+    return err != hipSuccess ? err : hipGetLastError();
+  }
+  if (ev.start != nullptr) {
+    const hipError_t err = hipEventRecord(ev.start, stream);
+    if (err != hipSuccess) return err;
+  }
+  hipError_t err = hipLaunchKernel(fn, grid, block, args, 0, stream);
+  if (err == hipSuccess && ev.stop != nullptr) err = hipEventRecord(ev.stop, stream);
+  return err != hipSuccess ? err : hipGetLastError();
+}
+
+int member_run_blocks_per_cu(int sweeps, int region, bool fp32) {
+  const void* fn = member_run_kernel(sweeps, region, fp32);
+  if (fn == nullptr) return 0;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, member_run_threads(region), 0) !=
+      hipSuccess)
+    return 0;
+  return n;
 }
 
 hipError_t launch_interleave(const double* p, const double* q, double2* out, int n,

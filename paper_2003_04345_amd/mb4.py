@@ -122,6 +122,9 @@ _SIGNATURES = {
     "mb4_ensemble_sweeps": (c_int32, [c_void_p]),
     "mb4_ensemble_tune_all": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
                                       POINTER(c_double)]),
+    "mb4_ensemble_set_persistent": (c_int, [c_void_p, c_int32]),
+    "mb4_ensemble_persistent": (c_int32, [c_void_p]),
+    "mb4_ensemble_tune_launch": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_double)]),
     "mb4_server_create": (c_int, [c_uint64, c_int32, c_int32, POINTER(mb4_options),
                                   POINTER(c_void_p)]),
     "mb4_server_destroy": (None, [c_void_p]),
@@ -595,6 +598,24 @@ class MB4Ensemble:
                  for sw in range(4) for r in range(MB4_REGION_COUNT)
                  if ms[sw * MB4_REGION_COUNT + r] >= 0}
         return region.value, sweeps.value, times
+
+    def set_persistent(self, on: bool) -> None:
+        """One persistent launch per batch (True) or one launch per Newton
+        phase (False, the default); the same results bit for bit."""
+        _check(load_library().mb4_ensemble_set_persistent(self._e, 1 if on else 0),
+               "mb4_ensemble_set_persistent")
+
+    def persistent(self) -> bool:
+        return load_library().mb4_ensemble_persistent(self._e) == 1
+
+    def tune_launch(self, steps: int = 32) -> tuple[bool, list[float]]:
+        """Autotuner over the launch form at the current region and sweeps:
+        (persistent kept, [ms per step per-phase, persistent])."""
+        pe = c_int32()
+        ms = (c_double * 2)()
+        _check(load_library().mb4_ensemble_tune_launch(self._e, int(steps), byref(pe), ms),
+               "mb4_ensemble_tune_launch")
+        return pe.value == 1, list(ms)
 
     def close(self) -> None:
         if getattr(self, "_e", None) is not None:
