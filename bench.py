@@ -166,11 +166,15 @@ def run_ensemble(args, torch, M) -> int:
         tuning = {"region": M.REGION_NAMES[region], "inner_sweeps": sweeps,
                   "ms_per_step": {f"{M.REGION_NAMES[r]}/{sw}": t
                                   for (r, sw), t in sorted(ms.items())}}
-        # The launch form at that shape: one launch per Newton phase, or one
-        # persistent launch per batch (the faster is kept).
-        persistent, form_ms = ens.tune_launch(args.tune_steps)
-        tuning["launch_form"] = "persistent" if persistent else "per-phase"
-        tuning["launch_form_ms_per_step"] = {"per-phase": form_ms[0], "persistent": form_ms[1]}
+        if args.launch_form == "tuned":
+            # The launch form at that shape: one launch per Newton phase, or
+            # one persistent launch per batch (the faster is kept).
+            persistent, form_ms = ens.tune_launch(args.tune_steps)
+            tuning["launch_form"] = "persistent" if persistent else "per-phase"
+            tuning["launch_form_ms_per_step"] = {"per-phase": form_ms[0],
+                                                 "persistent": form_ms[1]}
+    if args.launch_form != "tuned":
+        ens.set_persistent(args.launch_form == "persistent")
     if args.warmup:
         if ens.step(args.warmup) != M.MB4_OK:
             raise RuntimeError(f"warmup failed: {M.error_detail()}")
@@ -199,6 +203,7 @@ def run_ensemble(args, torch, M) -> int:
     h_end = ens.energies()
     drift = float(np.max(np.abs(h_end - h_start) / np.abs(h_start)))
     iters = [ens.member_stats(i)["newton_iters"] for i in range(len(members))]
+    ens_form = ens.persistent()
     ens.close()
     sites = sum(m.nx * m.ny for m in members)
     it = max(iters)
@@ -219,6 +224,7 @@ def run_ensemble(args, torch, M) -> int:
         "energy_drift": drift, "energy_drift_ok": drift <= 1e-14, "energy_drift_steps": steps,
         "newton_iters_last": {"min": min(iters), "max": it},
         "tuning": tuning,
+        "launch_form": "persistent" if ens_form else "per-phase",
         "step_bandwidth": {"bytes_per_site_step": step_bytes_per_site(it),
                            "achieved_GBs": step_bytes / (elapsed / steps) / 1e9,
                            "peak_GBs": HBM_PEAK_GBS},
@@ -484,6 +490,9 @@ def main(argv=None) -> int:
     ap.add_argument("--tune-steps", type=int, default=32,
                     help="steps the autotuner times per region/sweeps pair (0: no tuning; "
                          "not for the continuum workloads)")
+    ap.add_argument("--launch-form", choices=("tuned", "per-phase", "persistent"), default="tuned",
+                    help="ensemble128: one launch per Newton phase, one persistent launch per "
+                         "batch, or the faster of the two (tuned, with the tuner on)")
     ap.add_argument("--eps", type=float, default=0.0, help="Newton tolerance (0: library default)")
     ap.add_argument("--sweeps", type=int, default=0, help="block-Jacobi sweeps (0: default)")
     ap.add_argument("--fp32-solve", action="store_true",
