@@ -66,7 +66,7 @@ def build_library(verbose: bool = False) -> str:
     gen = os.path.join(CSRC, "gen_constants.py")
     subprocess.run([sys.executable, gen], check=True)
     tmp = LIB + ".tmp"
-    with tempfile.TemporaryDirectory(prefix="mb4_build_") as objdir:
+    with tempfile.TemporaryDirectory(prefix="_build_obj_", dir=PKG) as objdir:
         cmds = compile_commands(tmp, objdir)
         if verbose:
             for c in cmds:
