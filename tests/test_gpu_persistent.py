@@ -176,3 +176,28 @@ def test_tune_launch_keeps_the_trajectory():
         for i in range(len(MEMBERS)):
             assert all(np.array_equal(x, y) for x, y in zip(a.get_state(i), b.get_state(i))), i
             assert a.member_stats(i) == b.member_stats(i)
+
+
+def test_member_failing_at_an_odd_step_keeps_that_steps_state():
+    # A focusing member (g = -40) whose Newton iteration count grows from 12
+    # to 13 at step 11 (0-based) of its run: with max_newton = 12 it fails
+    # there, in the middle of a batch and on a step that reads the batch's
+    # second u_0 buffer.  Both forms keep the state after its 11 accepted
+    # steps, which is the single state's after 11 steps, bit for bit.
+    torch_cuda()
+    focus = L.config("lattice32", nx=8, ny=8, sigma=1.0, defect_count=1, seed=31, g=-40.0,
+                     h=0.01)
+    members = [MEMBERS[0], focus]
+    inputs = [L.make_inputs(m) for m in members]
+    ref = _run(members, inputs, False, 20, max_newton=12)
+    got = _run(members, inputs, True, 20, max_newton=12)
+    assert ref[0] == M.MB4_ENOCONV and "member 1" in got[1]
+    _assert_same(ref, got)
+    assert got[3][0]["steps_done"] == 20 and got[3][1]["steps_done"] == 11
+    v, p, q = inputs[1]
+    with M.MB4State(focus.nx, focus.ny, v, focus.g, focus.h) as st:
+        st.set_state(p, q)
+        assert st.step(11) == M.MB4_OK, M.error_detail()
+        assert st.last_stats()["newton_iters"] == 12
+        sp, sq = st.get_state()
+    assert np.array_equal(got[2][1][0], sp) and np.array_equal(got[2][1][1], sq)
