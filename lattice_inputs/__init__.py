@@ -17,7 +17,7 @@ ordering of Sec. 2.1, zero-based).
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field, asdict
+from dataclasses import asdict, dataclass, field, replace
 import math
 
 import numpy as np
@@ -218,6 +218,11 @@ CONFIGS: dict[str, LatticeProblem] = {
         sigma=32.0, kx=math.pi / 2, ky=math.pi / 4, h=0.005, steps=2000,
         seed=3),
 }
+# The 2048^2 workload with its packet centred on the lattice corner: the
+# packet wraps around all four edges, so the periodic wrap and the partial
+# right and top tiles of a full-size run carry signal.
+CONFIGS["lattice2048corner"] = replace(CONFIGS["lattice2048"], name="lattice2048corner",
+                                       centre=(0, 0))
 
 
 def continuum_hopping(n: int) -> float:

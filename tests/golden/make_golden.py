@@ -2,8 +2,8 @@
 
 Runs only the CPU oracle (oracle/) on the seeded workloads of lattice_inputs;
 nothing here touches the GPU library.  Usage:
-    python tests/golden/make_golden.py [lattice32] [lattice256] [lattice2048] [continuum70]
-                                       [delta100]
+    python tests/golden/make_golden.py [lattice32] [lattice256] [lattice2048]
+                                       [lattice2048corner] [continuum70] [delta100]
 
 Each JSON file holds the workload name, the number of steps, the Newton
 tolerance (and whether it is relative to ||u_0||_inf), the oracle's stage solver, the site indices compared (all sites,
@@ -34,6 +34,8 @@ CASES = {
     "lattice32": (1000, 1e-13, "direct", 100, False),
     "lattice256": (1000, 1e-13, "gmres", 100, True),
     "lattice2048": (20, 1e-13, "gmres", 5, True),
+    # The same with the packet on the lattice corner (wrapping every edge).
+    "lattice2048corner": (20, 1e-13, "gmres", 5, True),
     # The continuum runs of Sec. 3: the whole t in [0, 0.5] of the 70 x 70
     # comparison run, and the whole t in [0, 20] of the delta run.
     "continuum70": (50, 1e-13, "direct", 5, True),
@@ -45,14 +47,15 @@ RELATIVE = {"continuum70"}
 
 
 def sample_sites(cfg, n_packet=512, n_uniform=512, seed=2024):
-    """Half of the sample inside three packet widths of the centre, half
-    uniform over the lattice; fixed by the seed."""
+    """Half of the sample inside three packet widths of the packet's centre
+    (periodic distance), half uniform over the lattice; fixed by the seed."""
     rng = np.random.default_rng(seed)
+    cx, cy = (cfg.nx // 2, cfg.ny // 2) if cfg.centre is None else cfg.centre
     x = np.arange(cfg.nx)
     y = np.arange(cfg.ny)
-    dx = np.abs(x - cfg.nx // 2)
+    dx = np.abs(x - cx)
     dx = np.minimum(dx, cfg.nx - dx)
-    dy = np.abs(y - cfg.ny // 2)
+    dy = np.abs(y - cy)
     dy = np.minimum(dy, cfg.ny - dy)
     d2 = (dy[:, None] ** 2 + dx[None, :] ** 2).reshape(-1)
     near = np.flatnonzero(d2 <= (3 * cfg.sigma) ** 2)
