@@ -57,7 +57,7 @@ def _gpu_run(name, steps, eps, energy_every=0, relative_eps=False, fp32_solve=Fa
 
 
 @pytest.mark.parametrize("fp32_solve,tune", [(False, False), (True, False), (False, True)])
-@pytest.mark.parametrize("name", ["lattice32", "lattice256", "lattice2048"])
+@pytest.mark.parametrize("name", ["lattice32", "lattice256", "lattice2048", "lattice2048corner"])
 def test_workload_matches_stored_oracle_run(name, fp32_solve, tune):
     # Also with the FP32 inner solves, and with the tuned launch shape that
     # bench.py times, against the same FP64 oracle run.
@@ -74,6 +74,13 @@ def test_workload_matches_stored_oracle_run(name, fp32_solve, tune):
           f"max-abs {err:.3e} (max |psi| {scale:.3e})")
     # State parity bar of the workload definition: max-abs <= 1e-12 after the run.
     assert err <= 1e-12
+    if name == "lattice2048corner":
+        # The packet wraps every edge: sampled sites within one tile of an
+        # edge carry signal well above the bar.
+        cfg = L.CONFIGS[name]
+        x, y = sites % cfg.nx, sites // cfg.nx
+        edge = (np.minimum(x, cfg.nx - 1 - x) < 26) | (np.minimum(y, cfg.ny - 1 - y) < 26)
+        assert np.count_nonzero(edge & (np.abs(g["p"] + 1j * g["q"]) > 1e-4)) >= 100
     # Energies along the run agree with the oracle's (both compensated sums).
     ref = dict(g["energies"])
     for n, e in energies:
