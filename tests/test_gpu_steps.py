@@ -156,6 +156,31 @@ def test_non_finite_update_is_reported(fp32_solve):
         assert np.array_equal(pp, p) and np.array_equal(qq, q)
 
 
+def test_zero_steps_change_nothing():
+    # nsteps = 0 is a valid call that leaves the state, the step counter and
+    # the last statistics as they were, for a state and for an ensemble.
+    torch_cuda()
+    cfg = L.CONFIGS["lattice32"]
+    v, p, q = L.make_inputs(cfg)
+    with M.MB4State(cfg.nx, cfg.ny, v, cfg.g, cfg.h) as st:
+        st.set_state(p, q)
+        assert st.step(3) == M.MB4_OK
+        before, done, stats = st.get_state(), st.steps_done(), st.last_stats()
+        assert st.step(0) == M.MB4_OK
+        after = st.get_state()
+        assert all(np.array_equal(a, b) for a, b in zip(before, after))
+        assert st.steps_done() == done == 3 and st.last_stats() == stats
+    with M.MB4Ensemble([cfg, cfg], [v, v]) as ens:
+        ens.set_state(0, p, q)
+        ens.set_state(1, q, p)
+        assert ens.step(2) == M.MB4_OK
+        before = [ens.get_state(i) for i in range(2)]
+        assert ens.step(0) == M.MB4_OK
+        for i in range(2):
+            assert all(np.array_equal(a, b) for a, b in zip(before[i], ens.get_state(i)))
+            assert ens.member_stats(i)["steps_done"] == 2
+
+
 def test_zero_state_stays_zero():
     torch_cuda()
     cfg = L.CONFIGS["lattice32"]
