@@ -490,6 +490,9 @@ def main(argv=None) -> int:
     ap.add_argument("--tune-steps", type=int, default=32,
                     help="steps the autotuner times per region/sweeps pair (0: no tuning; "
                          "not for the continuum workloads)")
+    ap.add_argument("--repeats", type=int, default=2,
+                    help="single lattices without energy logging: repeat the timed call this "
+                         "many more times and report every run's ms per step and the median")
     ap.add_argument("--launch-form", choices=("tuned", "per-phase", "persistent"), default="tuned",
                     help="ensemble128: one launch per Newton phase, one persistent launch per "
                          "batch, or the faster of the two (tuned, with the tuner on)")
@@ -613,6 +616,17 @@ def main(argv=None) -> int:
     drift = abs(h_end - h_start) / abs(h_start)
     stats = st.last_stats()
     region_used, sweeps_used = st.region(), st.sweeps()
+    # The same timed call repeated on the evolved state (no logging runs
+    # only), for the spread of the measurement; `value` is the first run's.
+    repeats = [elapsed * 1e3 / steps]
+    if not continuum and not log_every:
+        for _ in range(max(0, args.repeats)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if st.step(steps) != M.MB4_OK:
+                raise RuntimeError(f"repeat run failed: {M.error_detail()}")
+            torch.cuda.synchronize()
+            repeats.append((time.perf_counter() - t1) * 1e3 / steps)
     # Per-kernel timing: the same workload continued for up to 200 steps with
     # every launch timed by HIP events in its dispatch packet (launched one by
     # one, since the events belong to individual launches).
@@ -638,6 +652,8 @@ def main(argv=None) -> int:
         "warmup": args.warmup,
         "ms_per_step": elapsed * 1e3 / steps,
         "ms_per_step_hip_events": event_ms / steps,
+        "ms_per_step_runs": repeats,
+        "ms_per_step_median": float(np.median(repeats)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
