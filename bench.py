@@ -71,6 +71,21 @@ BYTES_PER_SITE = {
 }
 
 
+# The paper's own figures, on other hardware: context for the bench lines,
+# not a target (the paper gives no absolute throughput of its parallel
+# solver and no GPU figures).
+PAPER_CONTEXT = {
+    "parallel_speedup": 2.79,
+    "parallel_speedup_setup": ("its stage-parallel solver on 3 nodes (one stage solve each) "
+                               "against 1 node; 2 x Xeon E5-2695v4 (18 cores, 2.1 GHz) per node, "
+                               "108 threads, MPI and a sparse direct solver; grids 40^2 to 640^2 "
+                               "(Sec. 3.2)"),
+    "seconds_per_step_70x70": 46.2,
+    "seconds_per_step_70x70_setup": ("MATLAB, dense stage solves, the 70 x 70 comparison grid "
+                                     "(Table 1, Sec. 3.1): about 106 lattice-site-steps/s"),
+}
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for name in ("mb4_kernels.hip", "mb4_internal.h", "mb4_constants.h"):
@@ -221,6 +236,7 @@ def run_ensemble(args, torch, M) -> int:
                    "sigma": members[0].sigma, "seeds": f"1000..{999 + len(members)}",
                    "parallelism": "single GPU, all members per launch",
                    "newton_eps": args.eps or 1e-13, "newton_test": "absolute (Algorithm 1)"},
+        "paper_context": PAPER_CONTEXT,
         "energy_drift": drift, "energy_drift_ok": drift <= 1e-14, "energy_drift_steps": steps,
         "newton_iters_last": {"min": min(iters), "max": it},
         "tuning": tuning,
@@ -666,6 +682,7 @@ def main(argv=None) -> int:
                    "newton_eps": args.eps or 1e-13, "newton_test": "absolute (Algorithm 1)",
                    "inner_sweeps": stats["inner_sweeps"] // max(stats["newton_iters"], 1),
                    "region": M.REGION_NAMES[region_used]},
+        "paper_context": PAPER_CONTEXT,
         "energy_drift": drift,
         "energy_drift_ok": drift <= 1e-14,
         # |H(end) - H(start)| / |H(start)| over exactly the timed steps.
