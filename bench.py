@@ -486,6 +486,90 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def write_traffic(prof_dir: str, out_path: str, copy_mib: int = 512) -> int:
+    """profiles/traffic.json from the 2048^2 counter runs in prof_dir (rocprofv3
+    CSV output in pmc_fetch/, pmc_write/ and, for the 512 MiB copy
+    calibration, pmc_fetch_copy/ and pmc_write_copy/; the commands are in
+    profiles/mb4_kernels_lattice2048.md).  Each counter is scaled by what it
+    reads for the copy of known size.  The two kinds of k_iterate launch (the
+    one writing X^2 and the batch's last iteration, writing X_3 alone)
+    alternate within every step; the write counter tells them apart and the
+    fetch run's dispatches follow the same order.  Host only."""
+    import collections
+    import csv
+
+    def short(name):
+        return name.replace("void ", "").replace("mb4::(anonymous namespace)::", "").split("(")[0]
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    acc[short(r["Kernel_Name"])].append(
+                        (int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        for k in acc:
+            acc[k].sort()
+        return acc
+
+    def csv_in(sub):
+        names = [n for n in os.listdir(os.path.join(prof_dir, sub))
+                 if n.endswith("_counter_collection.csv")]
+        if len(names) != 1:
+            raise RuntimeError(f"expected one counter CSV in {sub}, found {names}")
+        return os.path.join(prof_dir, sub, names[0])
+
+    copy = "__amd_rocclr_copyBuffer"
+    cf = per_kernel(csv_in("pmc_fetch_copy"), "FETCH_SIZE")[copy]
+    cw = per_kernel(csv_in("pmc_write_copy"), "WRITE_SIZE")[copy]
+    kib = copy_mib * 1024
+    ff = kib / (sum(v for _, v in cf) / len(cf))
+    wf = kib / (sum(v for _, v in cw) / len(cw))
+    fe = per_kernel(csv_in("pmc_fetch"), "FETCH_SIZE")
+    wr = per_kernel(csv_in("pmc_write"), "WRITE_SIZE")
+    cfg = L.CONFIGS["lattice2048"]
+    sites = cfg.sites
+
+    def b_per_site(kib_value, factor):
+        return kib_value * 1024 * factor / sites
+
+    it = "k_iterate<32, 32, 2, double>"
+    wi, fi = [v for _, v in wr[it]], [v for _, v in fe[it]]
+    if len(wi) % 2 or len(fi) != len(wi):
+        raise RuntimeError("k_iterate dispatches do not pair up into the two launch kinds")
+    w_full, w_last = wi[0::2], wi[1::2]
+    if not min(b_per_site(v, wf) for v in w_full) > max(b_per_site(v, wf) for v in w_last):
+        raise RuntimeError("the k_iterate dispatches do not alternate between the two kinds")
+
+    def entry(fvals, wvals, alg):
+        fb = b_per_site(sum(fvals) / len(fvals), ff)
+        wb = b_per_site(sum(wvals) / len(wvals), wf)
+        return {"bytes_per_site": round(fb + wb, 2), "fetch_bytes_per_site": round(fb, 2),
+                "write_bytes_per_site": round(wb, 2), "dispatches": len(fvals),
+                "algorithmic_bytes_per_site": alg}
+
+    def entry_k(name, alg):
+        return entry([v for _, v in fe[name]], [v for _, v in wr[name]], alg)
+
+    full = entry(fi[0::2], w_full, BYTES_PER_SITE["iterate"])
+    out = {"workload": cfg.name, "sites": sites, "region": "32x32", "inner_sweeps": 3,
+           "kernel_source_digest": kernel_source_digest(),
+           "calibration": {"copy_mib": copy_mib, "fetch_factor": round(ff, 4),
+                           "write_factor": round(wf, 4)},
+           "kernels": {
+               "stage_solve_first": entry_k("k_stage_solve<32, 32, 2, 2, double>",
+                                            BYTES_PER_SITE["stage_solve_first"]),
+               "iterate": full, "iterate_first": dict(full),
+               "iterate_last": entry(fi[1::2], w_last, BYTES_PER_SITE["iterate_last"]),
+               "final_update": entry_k("k_final_update", BYTES_PER_SITE["final_update"]),
+               "final_first": entry_k("k_stage_solve<32, 32, 2, 3, double>",
+                                      BYTES_PER_SITE["final_first"])}}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out["kernels"]), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,7 +616,12 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM "
                          "byte counters) and exit")
+    ap.add_argument("--write-traffic", default="", metavar="DIR",
+                    help="only write profiles/traffic.json from the 2048^2 counter runs in DIR "
+                         "(host only) and exit")
     args = ap.parse_args(argv)
+    if args.write_traffic:
+        return write_traffic(args.write_traffic, os.path.join(ROOT, "profiles", "traffic.json"))
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
 
